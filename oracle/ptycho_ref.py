@@ -1,0 +1,360 @@
+"""FP64 CPU oracle for the far-field ptychographic forward model and its exact adjoint.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import, call or execute
+this module: only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark use it. It shares no code with the GPU library.
+
+What it computes (arxiv 2510.20929, Pty-Chi):
+  * the forward model of Sec. 2.1 (patch extraction, exit wave psi = p * o, free-space
+    propagation to the far field, several incoherent probe modes, scan-point-specific
+    probes from orthogonal probe relaxation, multislice), giving the predicted
+    intensity I_p = F(o, p, Lambda) of Eq. (4);
+  * the Gaussian (magnitude MSE) loss of Eq. (1), and a Poisson negative
+    log-likelihood (the paper names no formula; reading below);
+  * the gradients of that loss: the object-patch gradient has the form of Eq. (2)
+    (conjugate probe times the difference between the magnitude-updated and the
+    forward exit wave), extended to the probe, the OPR weights, the scan positions
+    and every multislice slice by the chain rule.
+
+Readings where the paper is silent (each is a documented choice, not a derivation):
+  * FFT: unitary ("ortho") 2D DFT with kernel exp(-2 pi i k.n / N).
+  * Detector arrays (measured and predicted intensity) are DC-centred (fftshift).
+  * Position r = (y, x) is the frame's top-left corner in object pixels; the patch is
+    the bilinear interpolation of the object at the fractional offset; taps whose
+    weight is exactly zero are not read.  The window is N x N, widened by one row
+    (column) when the fraction is non-zero or position gradients are requested.
+    A window outside the object raises ValueError.
+  * Gradient convention: g = dL/dRe z + i dL/dIm z (twice the conjugate Wirtinger
+    derivative; 2 x the value printed in Eq. (2)).
+  * Loss normaliser 1 / (K_norm N^2); K_norm defaults to the number of positions.
+  * Poisson: l = I - I_meas ln(I + eps), eps in photons, constants dropped.
+  * Amplitude loss: the ratio I_meas / I floors I at 1e-30.
+  * OPR: P_{k,m} = sum_e w_{k,e} U_{e,m} with real w, applied to every mode.
+  * Multislice: transmit, then propagate by H = exp(-i pi lz (fy^2 + fx^2)) (fy, fx in
+    cycles per pixel), S - 1 propagations, the last exit wave goes to the far field;
+    every slice uses the same position.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+AMP_FLOOR = 1e-30
+
+
+# ----------------------------------------------------------------------------- transforms
+
+def fft2u(x: np.ndarray) -> np.ndarray:
+    """Unitary 2D DFT over the last two axes (forward kernel exp(-2 pi i k n / N))."""
+    return np.fft.fft2(x, norm="ortho")
+
+
+def ifft2u(x: np.ndarray) -> np.ndarray:
+    """Inverse of ``fft2u`` (its adjoint, since the transform is unitary)."""
+    return np.fft.ifft2(x, norm="ortho")
+
+
+def dft2_bruteforce(x: np.ndarray) -> np.ndarray:
+    """The same unitary 2D DFT written as explicit sums over a DFT matrix (slow pin)."""
+    n = x.shape[-1]
+    k = np.arange(n)
+    F = np.exp(-2j * math.pi * np.outer(k, k) / n) / math.sqrt(n)
+    return F @ x.astype(np.complex128) @ F.T
+
+
+def centre(a: np.ndarray) -> np.ndarray:
+    """Unshifted detector layout -> DC-centred layout."""
+    return np.fft.fftshift(a, axes=(-2, -1))
+
+
+def uncentre(a: np.ndarray) -> np.ndarray:
+    """DC-centred detector layout -> unshifted layout."""
+    return np.fft.ifftshift(a, axes=(-2, -1))
+
+
+def fresnel_tf(N: int, lambda_z: float) -> np.ndarray:
+    """Free-space transfer function exp(-i pi lz (fy^2 + fx^2)) on the unshifted grid."""
+    f = np.fft.fftfreq(N)
+    fy, fx = np.meshgrid(f, f, indexing="ij")
+    return np.exp(-1j * math.pi * lambda_z * (fy * fy + fx * fx))
+
+
+def propagate(x: np.ndarray, tf: np.ndarray) -> np.ndarray:
+    """Slice-to-slice propagation: inverse DFT of the transfer function times the DFT."""
+    return ifft2u(tf * fft2u(x))
+
+
+def propagate_adjoint(g: np.ndarray, tf: np.ndarray) -> np.ndarray:
+    return ifft2u(np.conj(tf) * fft2u(g))
+
+
+# ----------------------------------------------------------------------------- patches
+
+def split_position(r: Sequence[float], N: int, H: int, W: int, want_pos: bool):
+    """Integer corner and fraction of one scan position, with the window bounds check."""
+    ry, rx = float(r[0]), float(r[1])
+    y0, x0 = int(math.floor(ry)), int(math.floor(rx))
+    fy, fx = ry - y0, rx - x0
+    ey = 1 if (fy > 0.0 or want_pos) else 0
+    ex = 1 if (fx > 0.0 or want_pos) else 0
+    if y0 < 0 or x0 < 0 or y0 + N - 1 + ey > H - 1 or x0 + N - 1 + ex > W - 1:
+        raise ValueError(f"scan window at {(ry, rx)} leaves the {H}x{W} object")
+    return y0, x0, fy, fx
+
+
+def _taps(fy: float, fx: float):
+    """Bilinear taps (a, b, weight) with the zero-weight ones dropped."""
+    out = []
+    for a, wa in ((0, 1.0 - fy), (1, fy)):
+        if wa == 0.0:
+            continue
+        for b, wb in ((0, 1.0 - fx), (1, fx)):
+            if wb == 0.0:
+                continue
+            out.append((a, b, wa * wb))
+    return out
+
+
+def extract_patch(Os: np.ndarray, y0: int, x0: int, fy: float, fx: float, N: int) -> np.ndarray:
+    """Object patch at a sub-pixel position: bilinear interpolation of one slice."""
+    o = np.zeros((N, N), dtype=np.complex128)
+    for a, b, w in _taps(fy, fx):
+        o += w * Os[y0 + a:y0 + a + N, x0 + b:x0 + b + N]
+    return o
+
+
+def scatter_patch(gOs: np.ndarray, g: np.ndarray, y0: int, x0: int, fy: float, fx: float) -> None:
+    """Transpose of ``extract_patch``: add the patch gradient back into the slice."""
+    N = g.shape[-1]
+    for a, b, w in _taps(fy, fx):
+        gOs[y0 + a:y0 + a + N, x0 + b:x0 + b + N] += w * g
+
+
+def patch_derivatives(Os: np.ndarray, y0: int, x0: int, fy: float, fx: float, N: int):
+    """d(patch)/dy and d(patch)/dx of the bilinear patch (right derivative at integers)."""
+    A = Os[y0:y0 + N + 1, x0:x0 + N + 1].astype(np.complex128)
+    dy = (1.0 - fx) * (A[1:, :-1] - A[:-1, :-1]) + fx * (A[1:, 1:] - A[:-1, 1:])
+    dx = (1.0 - fy) * (A[:-1, 1:] - A[:-1, :-1]) + fy * (A[1:, 1:] - A[1:, :-1])
+    return dy, dx
+
+
+def probe_for_position(U: np.ndarray, w_k: Optional[np.ndarray]) -> np.ndarray:
+    """Scan-point probe modes [M, N, N]: the weighted sum of the eigenprobes."""
+    if w_k is None:
+        return U[0].astype(np.complex128)
+    return np.tensordot(w_k.astype(np.float64), U.astype(np.complex128), axes=(0, 0))
+
+
+# ----------------------------------------------------------------------------- loss
+
+def loss_and_factor(I: np.ndarray, Im: np.ndarray, loss: str, eps: float):
+    """Per-pixel loss and dl/dI for the amplitude (Eq. (1)) or Poisson loss."""
+    if loss == "amplitude":
+        l = (np.sqrt(I) - np.sqrt(Im)) ** 2
+        c = 1.0 - np.sqrt(Im / np.maximum(I, AMP_FLOOR))
+    elif loss == "poisson":
+        l = I - Im * np.log(I + eps)
+        c = 1.0 - Im / (I + eps)
+    else:
+        raise ValueError(f"unknown loss {loss!r}")
+    return l, c
+
+
+# ----------------------------------------------------------------------------- model
+
+def _as_inputs(obj, probe, positions, weights):
+    O = np.asarray(obj).astype(np.complex128)
+    if O.ndim == 2:
+        O = O[None]
+    U = np.asarray(probe).astype(np.complex128)
+    if U.ndim == 3:
+        U = U[None]
+    r = np.asarray(positions).astype(np.float64).reshape(-1, 2)
+    w = None if weights is None else np.asarray(weights).astype(np.float64).reshape(r.shape[0], -1)
+    if w is None and U.shape[0] != 1:
+        raise ValueError("several eigenprobes need weights")
+    if w is not None and w.shape[1] != U.shape[0]:
+        raise ValueError("weights must have one column per eigenprobe")
+    return O, U, r, w
+
+
+def _forward_one(O, P, y0, x0, fy, fx, tf):
+    """Exit waves of one position. Returns (patches o_s, incident waves psi_s [M,N,N]
+    per slice, far-field Psi [M,N,N])."""
+    S, N = O.shape[0], P.shape[-1]
+    patches = [extract_patch(O[s], y0, x0, fy, fx, N) for s in range(S)]
+    psis = []
+    psi = P
+    for s in range(S):
+        psis.append(psi)
+        chi = psi * patches[s][None]
+        if s < S - 1:
+            psi = propagate(chi, tf)
+    Psi = fft2u(chi)
+    return patches, psis, Psi
+
+
+def apply_A(obj, probe, positions, weights=None, lambda_z: float = 0.0) -> np.ndarray:
+    """Far-field waves Psi [K, M, N, N] (unshifted) of every position and mode."""
+    O, U, r, w = _as_inputs(obj, probe, positions, weights)
+    N = U.shape[-1]
+    tf = fresnel_tf(N, lambda_z) if O.shape[0] > 1 else None
+    out = np.empty((r.shape[0], U.shape[1], N, N), dtype=np.complex128)
+    for k in range(r.shape[0]):
+        y0, x0, fy, fx = split_position(r[k], N, O.shape[1], O.shape[2], False)
+        P = probe_for_position(U, None if w is None else w[k])
+        out[k] = _forward_one(O, P, y0, x0, fy, fx, tf)[2]
+    return out
+
+
+def _backward_one(O, U, w_k, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
+                  gO, gU, want_w: bool):
+    """Adjoint of one position given dL/dPsi (g convention) for every mode.
+    Accumulates into gO, gU; returns (per-slice patch gradients, dL/dw_k)."""
+    S = O.shape[0]
+    g = ifft2u(gPsi)                                # [M, N, N] gradient of the last exit wave
+    g_patch = [None] * S
+    for s in range(S - 1, -1, -1):
+        g_patch[s] = np.sum(np.conj(psis[s]) * g, axis=0)
+        g_psi = np.conj(patches[s])[None] * g       # gradient of the incident wave psi_s
+        if s > 0:
+            g = propagate_adjoint(g_psi, tf)
+        else:
+            g = g_psi
+    gP = g                                          # gradient of the scan-point probe modes
+    if w_k is None:
+        gU[0] += gP
+    else:
+        gU += w_k[:, None, None, None] * gP[None]
+    gw = None
+    if want_w:
+        gw = np.array([float(np.sum(np.real(np.conj(gP) * U[e]))) for e in range(U.shape[0])])
+    for s in range(S):
+        scatter_patch(gO[s], g_patch[s], y0, x0, fy, fx)
+    return g_patch, gw
+
+
+def apply_AH(Y, obj, probe, positions, weights=None, lambda_z: float = 0.0):
+    """Adjoint of the maps O_s -> Psi (other slices and probe fixed) and U -> Psi
+    (object fixed), applied to Y [K, M, N, N].  Returns (g_obj [S,H,W], g_probe [E,M,N,N])."""
+    O, U, r, w = _as_inputs(obj, probe, positions, weights)
+    Y = np.asarray(Y).astype(np.complex128)
+    N = U.shape[-1]
+    tf = fresnel_tf(N, lambda_z) if O.shape[0] > 1 else None
+    gO = np.zeros_like(O)
+    gU = np.zeros_like(U)
+    for k in range(r.shape[0]):
+        y0, x0, fy, fx = split_position(r[k], N, O.shape[1], O.shape[2], False)
+        wk = None if w is None else w[k]
+        P = probe_for_position(U, wk)
+        patches, psis, _ = _forward_one(O, P, y0, x0, fy, fx, tf)
+        _backward_one(O, U, wk, P, patches, psis, Y[k], tf, y0, x0, fy, fx, gO, gU, False)
+    return gO, gU
+
+
+def forward(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
+            eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None):
+    """Loss L and the predicted intensity I_pred [K, N, N] (DC-centred)."""
+    out = forward_adjoint(obj, probe, positions, I_meas, weights=weights, loss=loss, eps=eps,
+                          lambda_z=lambda_z, norm_count=norm_count, grads=())
+    return out["loss"], out["I_pred"]
+
+
+def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
+                    eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None,
+                    grads: Sequence[str] = ("obj", "probe")) -> Dict[str, np.ndarray]:
+    """Loss, predicted intensity and the requested gradients
+    (any of "obj", "probe", "pos", "weights")."""
+    O, U, r, w = _as_inputs(obj, probe, positions, weights)
+    Im_all = np.asarray(I_meas).astype(np.float64)
+    K, N = r.shape[0], U.shape[-1]
+    S, H, W = O.shape
+    Kn = float(K if (norm_count is None or norm_count <= 0) else norm_count)
+    scale = 1.0 / (Kn * N * N)
+    tf = fresnel_tf(N, lambda_z) if S > 1 else None
+    want_pos = "pos" in grads
+    want_w = "weights" in grads
+    any_grad = len(grads) > 0
+    gO = np.zeros_like(O)
+    gU = np.zeros_like(U)
+    gr = np.zeros((K, 2))
+    gw = np.zeros((K, U.shape[0]))
+    I_pred = np.empty((K, N, N))
+    total = 0.0
+    for k in range(K):
+        y0, x0, fy, fx = split_position(r[k], N, H, W, want_pos)
+        wk = None if w is None else w[k]
+        P = probe_for_position(U, wk)
+        patches, psis, Psi = _forward_one(O, P, y0, x0, fy, fx, tf)
+        I = np.sum(np.abs(Psi) ** 2, axis=0)          # unshifted incoherent sum
+        Im = uncentre(Im_all[k])
+        l, c = loss_and_factor(I, Im, loss, eps)
+        total += float(np.sum(l))
+        I_pred[k] = centre(I)
+        if not any_grad:
+            continue
+        gPsi = (2.0 * scale) * c[None] * Psi
+        g_patch, gwk = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
+                                     gO, gU, want_w)
+        if want_w:
+            gw[k] = gwk
+        if want_pos:
+            for s in range(S):
+                dy, dx = patch_derivatives(O[s], y0, x0, fy, fx, N)
+                gr[k, 0] += float(np.sum(np.real(np.conj(g_patch[s]) * dy)))
+                gr[k, 1] += float(np.sum(np.real(np.conj(g_patch[s]) * dx)))
+    out: Dict[str, np.ndarray] = {"loss": total * scale, "I_pred": I_pred}
+    if "obj" in grads:
+        out["g_obj"] = gO
+    if "probe" in grads:
+        out["g_probe"] = gU
+    if want_pos:
+        out["g_pos"] = gr
+    if want_w:
+        out["g_weights"] = gw
+    return out
+
+
+def eq2_patch_gradient(obj, probe, position, I_meas, K_norm: float) -> np.ndarray:
+    """Eq. (2) as printed, for one position, one mode, one slice and the amplitude loss:
+    -(1/(B H W)) conj(p) (psi' - psi), with psi' the magnitude-updated wave brought back
+    to the exit plane.  (Used to pin the adjoint against the paper's own formula.)"""
+    O, U, r, _ = _as_inputs(obj, probe, position, None)
+    N = U.shape[-1]
+    y0, x0, fy, fx = split_position(r[0], N, O.shape[1], O.shape[2], False)
+    o = extract_patch(O[0], y0, x0, fy, fx, N)
+    p = U[0, 0]
+    psi = p * o
+    Psi = fft2u(psi)
+    Im = uncentre(np.asarray(I_meas, dtype=np.float64).reshape(N, N))
+    Psi_upd = np.sqrt(Im) * Psi / np.maximum(np.abs(Psi), math.sqrt(AMP_FLOOR))
+    psi_upd = ifft2u(Psi_upd)
+    return -(1.0 / (K_norm * N * N)) * np.conj(p) * (psi_upd - psi)
+
+
+def patch_gradients(obj, probe, positions, I_meas, *, weights=None, loss="amplitude", eps=1e-3,
+                    lambda_z=0.0, norm_count=None) -> np.ndarray:
+    """Per-position, per-slice patch gradients g_o [K, S, N, N] before the scatter."""
+    O, U, r, w = _as_inputs(obj, probe, positions, weights)
+    Im_all = np.asarray(I_meas).astype(np.float64)
+    K, N = r.shape[0], U.shape[-1]
+    S, H, W = O.shape
+    Kn = float(K if (norm_count is None or norm_count <= 0) else norm_count)
+    tf = fresnel_tf(N, lambda_z) if S > 1 else None
+    out = np.zeros((K, S, N, N), dtype=np.complex128)
+    for k in range(K):
+        y0, x0, fy, fx = split_position(r[k], N, H, W, False)
+        wk = None if w is None else w[k]
+        P = probe_for_position(U, wk)
+        patches, psis, Psi = _forward_one(O, P, y0, x0, fy, fx, tf)
+        I = np.sum(np.abs(Psi) ** 2, axis=0)
+        _, c = loss_and_factor(I, uncentre(Im_all[k]), loss, eps)
+        gPsi = (2.0 / (Kn * N * N)) * c[None] * Psi
+        gO = np.zeros_like(O)
+        gU = np.zeros_like(U)
+        g_patch, _ = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx, gO, gU, False)
+        for s in range(S):
+            out[k, s] = g_patch[s]
+    return out
