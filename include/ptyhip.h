@@ -1,0 +1,184 @@
+/*
+ * ptyhip — the data-parallel hot path of gradient-based ptychographic reconstruction
+ * (arxiv 2510.20929, "Pty-Chi") on AMD MI355X (gfx950): the batched far-field forward
+ * model and its exact adjoint, behind a plain C ABI.
+ *
+ * What the library computes (Sec. 2.1 forward model; Eq. (1); Eq. (2); Eq. (4)):
+ *   for each scan position k and probe mode m
+ *     o_k      = bilinear patch of the object at position r_k          (patch extraction)
+ *     P_{k,m}  = sum_e w_{k,e} U_{e,m}                                 (scan-point probes, OPR)
+ *     psi      = P_{k,m} * o_k, propagated through the slices          (exit wave; multislice)
+ *     Psi      = unitary 2D DFT of the last exit wave                  (far-field propagation)
+ *     I_k      = sum_m |Psi_{k,m}|^2                                   (incoherent modes)
+ *   L = sum_k sum_px l(I_k, I_meas_k) / (K_norm N^2), l = (sqrt(I) - sqrt(I_meas))^2
+ *   (Eq. (1)) or l = I - I_meas ln(I + eps) (Poisson), and the gradients of L with
+ *   respect to the object, the probe (eigenprobes), the positions and the OPR weights.
+ *
+ * Conventions (each is a reading of a point the paper leaves open):
+ *   - complex arrays are interleaved (re, im) float32 pairs ("complex64"), row-major;
+ *   - the DFT is unitary with kernel exp(-2 pi i k.n / N);
+ *   - measured and predicted intensities are DC-centred (fftshift layout);
+ *   - a position (y, x) is the frame's top-left corner in object pixels; the integer
+ *     part is the floor, the fraction drives bilinear interpolation; the window is
+ *     N x N, one row/column wider when the fraction is non-zero or position gradients
+ *     are requested;
+ *   - gradients are g = dL/dRe z + i dL/dIm z (the torch convention; twice Eq. (2));
+ *   - multislice: transmit then propagate by exp(-i pi lambda_z (fy^2 + fx^2)), S - 1
+ *     propagations, the last exit wave goes to the far field.
+ *
+ * Memory and ownership: every array argument of a call is a DEVICE pointer owned by
+ * the caller; the library never frees or retains it beyond the call. A plan owns its
+ * workspace (allocated once in ptyhip_plan_create, freed in ptyhip_plan_destroy);
+ * calls allocate nothing. Calls are asynchronous on `stream` (a hipStream_t, or NULL
+ * for the default stream). A plan is not re-entrant: one call in flight per plan.
+ *
+ * Errors: host-detectable problems (NULL pointers, bad shapes, K > max_positions,
+ * unsupported sizes) return a status and launch nothing. Problems only the device can
+ * see (a scan window leaving the object, non-finite inputs) set bits of a latched flag
+ * word in the plan; the offending position contributes nothing. Read it with
+ * ptyhip_get_error.
+ */
+#ifndef PTYHIP_H
+#define PTYHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PTYHIP_OK = 0,
+  PTYHIP_EINVAL = 1,       /* NULL pointer or invalid argument value */
+  PTYHIP_ESHAPE = 2,       /* inconsistent sizes */
+  PTYHIP_EBOUNDS = 3,      /* K outside [0, max_positions] */
+  PTYHIP_ENONFINITE = 4,   /* non-finite scalar parameter */
+  PTYHIP_EHIP = 5,         /* a HIP runtime call failed */
+  PTYHIP_ENOMEM = 6,       /* workspace allocation failed */
+  PTYHIP_EUNSUPPORTED = 7  /* size or option this build does not support */
+} ptyhip_status;
+
+typedef enum {
+  PTYHIP_LOSS_AMPLITUDE = 0, /* Gaussian magnitude loss, Eq. (1) */
+  PTYHIP_LOSS_POISSON = 1    /* l = I - I_meas ln(I + eps) (the paper names no formula) */
+} ptyhip_loss;
+
+/* flags of ptyhip_forward_adjoint / ptyhip_batch_launch */
+enum {
+  PTYHIP_GRAD_OBJ = 1,      /* object gradient               [S][H][W] complex */
+  PTYHIP_GRAD_PROBE = 2,    /* probe / eigenprobe gradient   [E][M][N][N] complex */
+  PTYHIP_GRAD_POS = 4,      /* position gradient             [K][2] float */
+  PTYHIP_GRAD_WEIGHTS = 8,  /* OPR weight gradient           [K][E] float */
+  PTYHIP_ACCUMULATE = 16,   /* add into the outputs (and loss) instead of overwriting */
+  PTYHIP_PLAIN = 32         /* run the per-step kernels instead of the fused kernel */
+};
+
+/* bits of the device error latch */
+enum { PTYHIP_FLAG_BOUNDS = 1, PTYHIP_FLAG_NONFINITE = 2 };
+
+/* Problem description. Sizes: N = frame, M = n_modes, E = n_eig, S = n_slices,
+ * object H x W per slice. */
+typedef struct {
+  int32_t frame;        /* N: 16, 32, 64, 128, 256 or 512 */
+  int32_t n_modes;      /* M: 1..64 incoherent probe modes (Sec. 2.1) */
+  int32_t n_eig;        /* E: 1..16 eigenprobes (OPR, Sec. 2.1); 1 = none */
+  int32_t n_slices;     /* S: 1..64 multislice slices (Sec. 2.1) */
+  int32_t obj_h, obj_w; /* object size per slice, >= N each */
+  int32_t loss;         /* ptyhip_loss */
+  float poisson_eps;    /* eps of the Poisson loss, photons (>= 0) */
+  float lambda_z;       /* slice spacing times wavelength, px^2 (used when S > 1) */
+  double norm_count;    /* K_norm of the 1/(K_norm N^2) normaliser; <= 0: K of the call */
+} ptyhip_desc;
+
+/* Optional implementation choices (the autotuner's search space). Zero = default. */
+typedef struct {
+  int32_t variant;      /* fused on-chip kernel thread layout: 0 = 512 threads, 1 = alternative */
+  int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
+  int32_t probe_copies; /* probe-gradient partial copies (1..8); 0 = 8 (one per XCD) */
+  int32_t recompute;    /* multislice: 1 = recompute incident waves, 0 = store them */
+  int32_t plain_chunk;  /* positions per chunk of the per-step path; 0 = auto */
+} ptyhip_tune;
+
+typedef struct {
+  size_t workspace_bytes;  /* device memory owned by the plan */
+  size_t scratch_bytes;    /* of which per-workgroup scratch of the fused kernel */
+  size_t plain_bytes;      /* of which per-step path buffers */
+  int32_t grid;            /* fused kernel workgroups */
+  int32_t threads;         /* fused kernel threads per workgroup */
+  int32_t fused_on_chip;   /* 1 if the frame stays on chip in the fused kernel */
+  int32_t plain_chunk;     /* positions per chunk of the per-step path */
+} ptyhip_plan_info;
+
+typedef struct ptyhip_plan_s* ptyhip_plan;
+typedef struct ptyhip_batch_s* ptyhip_batch;
+
+const char* ptyhip_status_str(ptyhip_status s);
+const char* ptyhip_version(void);
+
+/* Pure host check of a description; no GPU needed. */
+ptyhip_status ptyhip_desc_validate(const ptyhip_desc* desc);
+
+/* Create a plan for up to max_positions positions per call on the current device.
+ * tune may be NULL. Allocates the workspace; *out is NULL on failure. */
+ptyhip_status ptyhip_plan_create(const ptyhip_desc* desc, int32_t max_positions, ptyhip_plan* out);
+ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positions, const ptyhip_tune* tune,
+                                    ptyhip_plan* out);
+void ptyhip_plan_destroy(ptyhip_plan plan);
+ptyhip_status ptyhip_plan_get_info(ptyhip_plan plan, ptyhip_plan_info* info);
+
+/* Forward model and loss (Eq. (1) / Poisson) for K positions.
+ *   obj       [S][H][W] complex      probe   [E][M][N][N] complex
+ *   weights   [K][E] float or NULL (NULL requires E == 1 and means w = 1)
+ *   positions [K][2] float (y, x)    I_meas  [K][N][N] float, DC-centred
+ *   loss      device double[1] (written, or added to with PTYHIP_ACCUMULATE)
+ *   I_pred    [K][N][N] float DC-centred, or NULL */
+ptyhip_status ptyhip_forward(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,
+                             const float* weights, const float* positions, const float* I_meas, double* loss,
+                             float* I_pred);
+
+/* Forward model, loss and the gradients selected by `flags` (Eq. (2) extended to every
+ * parameter by the chain rule). Gradient outputs not requested may be NULL:
+ *   g_obj [S][H][W] complex, g_probe [E][M][N][N] complex, g_pos [K][2], g_weights [K][E].
+ * Outputs are overwritten unless PTYHIP_ACCUMULATE is set. I_pred may be NULL. */
+ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
+                                     const float* probe, const float* weights, const float* positions,
+                                     const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                     float* g_probe, float* g_pos, float* g_weights);
+
+/* The linear map (object, probe) -> far-field waves Psi [K][M][N][N] (unshifted),
+ * and its adjoint (for the identity <A x, y> = <x, A^H y>): apply_AH takes Y [K][M][N][N]
+ * and returns, per slice, the adjoint of O_s -> Psi (other slices and probe fixed) in
+ * g_obj and the adjoint of U -> Psi (object fixed) in g_probe (either may be NULL). */
+ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,
+                             const float* weights, const float* positions, float* Psi);
+ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const float* Y, const float* obj,
+                              const float* probe, const float* weights, const float* positions, float* g_obj,
+                              float* g_probe);
+
+/* Synchronise `stream` and read the plan's device error latch (PTYHIP_FLAG_*). */
+ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);
+/* Clear the latch (asynchronously on `stream`). */
+ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
+
+/* Many independent reconstructions of uneven frame sizes in one persistent launch,
+ * captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
+ * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. */
+ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, int32_t n, const ptyhip_tune* tune,
+                                  ptyhip_batch* out);
+/* Bind dataset i's device arrays (same meaning as in ptyhip_forward_adjoint). Rebinding
+ * updates a device descriptor table; a captured graph stays valid. */
+ptyhip_status ptyhip_batch_bind(ptyhip_batch b, int32_t i, const float* obj, const float* probe,
+                                const float* weights, const float* positions, const float* I_meas, double* loss,
+                                float* g_obj, float* g_probe, float* g_pos, float* g_weights);
+/* Run every dataset (flags as in ptyhip_forward_adjoint; PTYHIP_PLAIN runs one
+ * non-captured per-dataset call each instead). The first call with given flags captures
+ * a graph on `stream`; later calls replay it. */
+ptyhip_status ptyhip_batch_launch(ptyhip_batch b, void* stream, uint32_t flags);
+ptyhip_status ptyhip_batch_get_error(ptyhip_batch b, void* stream, uint32_t* flags);
+void ptyhip_batch_destroy(ptyhip_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTYHIP_H */

@@ -1,0 +1,395 @@
+// Complex FFTs for ptychographic frames on gfx950.
+//
+// A length-N transform is split as N = N1 * N2 (N1 <= N2): with input index
+// n = n1 + N1 n2 and output index k = k2 + N2 k1,
+//   X[k2 + N2 k1] = sum_n1 W_N^{n1 k2} W_N1^{n1 k1} sum_n2 x[n1 + N1 n2] W_N2^{n2 k2},
+// i.e. N1 register DFTs of size N2, a twiddle W_N^{n1 k2}, then N2 register DFTs of
+// size N1. The two register stages exchange data through LDS. A 2D N x N transform
+// runs that over the rows and then over the columns (4 register stages, 3 LDS
+// exchanges). The inverse runs the adjoint stages in reverse order, so a forward
+// transform leaves each thread holding exactly the frequencies its inverse needs,
+// and the inverse returns every pixel to the thread that supplied it.
+//
+// All transforms here are unnormalised; callers apply 1/N per 2D transform
+// (the unitary convention).
+#pragma once
+#include "common.hpp"
+
+namespace ptyhip {
+
+// ----------------------------------------------------------------------------- register DFTs
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<1, INV> {
+  __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    float2 s13 = cadd(v[1], v[3]), d13 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+// Cooley-Tukey split R = A * B with constant twiddles (register renaming only).
+template <int A, int B, bool INV>
+__device__ __forceinline__ void dft_split(float2* v) {
+  constexpr int R = A * B;
+  float2 t[R];
+  static_for<0, A>([&](auto n1c) {
+    constexpr int n1 = decltype(n1c)::value;
+    float2 u[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) u[n2] = v[n1 + A * n2];
+    Dft<B, INV>::run(u);
+    static_for<0, B>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      t[n1 * B + k2] = twiddle_const<R, n1 * k2, INV>(u[k2]);
+    });
+  });
+#pragma unroll
+  for (int k2 = 0; k2 < B; ++k2) {
+    float2 u[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) u[n1] = t[n1 * B + k2];
+    Dft<A, INV>::run(u);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) v[k2 + B * k1] = u[k1];
+  }
+}
+
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(float2* v) { dft_split<2, 4, INV>(v); }
+};
+template <bool INV>
+struct Dft<16, INV> {
+  __device__ __forceinline__ static void run(float2* v) { dft_split<4, 4, INV>(v); }
+};
+template <bool INV>
+struct Dft<32, INV> {
+  __device__ __forceinline__ static void run(float2* v) { dft_split<4, 8, INV>(v); }
+};
+
+// ----------------------------------------------------------------------------- factorisations
+template <int N>
+struct Split;
+template <> struct Split<16>  { static constexpr int N1 = 4,  N2 = 4;  };
+template <> struct Split<32>  { static constexpr int N1 = 4,  N2 = 8;  };
+template <> struct Split<64>  { static constexpr int N1 = 8,  N2 = 8;  };
+template <> struct Split<128> { static constexpr int N1 = 8,  N2 = 16; };
+template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
+template <> struct Split<512> { static constexpr int N1 = 16, N2 = 32; };
+
+// ----------------------------------------------------------------------------- on-chip 2D frame
+// A whole N x N frame spread over T threads (N <= 128). Each thread owns E elements.
+//
+// Layout A (pixels): element v[l*N2 + j] of thread t is pixel (y, x) with slot
+//   s = t + T l, y = s / N1, x = (s % N1) + N1 j.
+// Layout D (frequencies): element v[l*N2 + jj*N1 + l1] of thread t is frequency
+//   (ky, kx) with s = t + T l, kx = s % N, q = s / N, ky = (q + N1 jj) + N2 l1.
+//
+// LDS holds N rows of pitch P = N + N1 float2. Inside a row, the row-stage exchange
+// stores element (n1, k2) at N1 k2 + (n1 ^ (k2 mod N1)) so that both the writes and
+// the reads of that exchange touch distinct banks within each 16-lane group.
+template <int N, int T>
+struct Frame2D {
+  static constexpr int N1 = Split<N>::N1;
+  static constexpr int N2 = Split<N>::N2;
+  static constexpr int SLOTS = N * N1;
+  static_assert(SLOTS % T == 0, "thread count must divide N * N1");
+  static constexpr int L = SLOTS / T;
+  static constexpr int E = L * N2;
+  static constexpr int P = N + N1;
+  static constexpr int LDS_ELEMS = N * P;
+
+  __device__ __forceinline__ static int a_y(int t, int l) { return (t + T * l) / N1; }
+  __device__ __forceinline__ static int a_x(int t, int l, int j) { return (t + T * l) % N1 + N1 * j; }
+  __device__ __forceinline__ static int d_kx(int t, int l) { return (t + T * l) % N; }
+  // frequency row of element (l, i) with i = jj*N1 + l1 in layout D
+  __device__ __forceinline__ static int d_ky(int t, int l, int i) {
+    const int q = (t + T * l) / N;
+    const int jj = i / N1, l1 = i % N1;
+    return q + N1 * jj + N2 * l1;
+  }
+  __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ (k2 & (N1 - 1))); }
+
+  // layout A (pixels) -> layout D (frequencies), times `scale`
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2* lds, const float2* __restrict__ tw_,
+                                                 float scale) {
+    const int t = opaque_tid();
+    const float2* __restrict__ tw = opaque_ptr(tw_);
+    __syncthreads();
+    // row stage 1: DFT over n2, twiddle, exchange
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, n1 = s % N1;
+      float2* u = &v[l * N2];
+      Dft<N2, false>::run(u);
+#pragma unroll
+      for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul(u[k2], tw[n1 * k2]);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) lds[y * P + sw(n1, k2)] = u[k2];
+    }
+    __syncthreads();
+    // row stage 2: DFT over n1 for the thread's k2 values
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, q = s % N1;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) {
+        const int k2 = q + N1 * jj;
+        float2* u = &v[l * N2 + jj * N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) u[n1] = lds[y * P + sw(n1, k2)];
+        Dft<N1, false>::run(u);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, q = s % N1;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj)
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) lds[y * P + q + N1 * jj + N2 * k1] = v[l * N2 + jj * N1 + k1];
+    }
+    __syncthreads();
+    // column stage 1: thread owns column kx, residue m1; DFT over m2, twiddle
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, m1 = s / N;
+      float2* u = &v[l * N2];
+#pragma unroll
+      for (int m2 = 0; m2 < N2; ++m2) u[m2] = lds[(m1 + N1 * m2) * P + kx];
+      Dft<N2, false>::run(u);
+#pragma unroll
+      for (int l2 = 1; l2 < N2; ++l2) u[l2] = cmul(u[l2], tw[m1 * l2]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, m1 = s / N;
+#pragma unroll
+      for (int l2 = 0; l2 < N2; ++l2) lds[(m1 + N1 * l2) * P + kx] = v[l * N2 + l2];
+    }
+    __syncthreads();
+    // column stage 2: DFT over m1
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, q = s / N;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) {
+        const int l2 = q + N1 * jj;
+        float2* u = &v[l * N2 + jj * N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) u[n1] = lds[(n1 + N1 * l2) * P + kx];
+        Dft<N1, false>::run(u);
+#pragma unroll
+        for (int l1 = 0; l1 < N1; ++l1) u[l1] = cscale(u[l1], scale);
+      }
+    }
+  }
+
+  // layout D (frequencies) -> layout A (pixels): the adjoint of `forward`, times `scale`
+  __device__ __forceinline__ static void inverse(float2 (&v)[E], float2* lds, const float2* __restrict__ tw_,
+                                                 float scale) {
+    const int t = opaque_tid();
+    const float2* __restrict__ tw = opaque_ptr(tw_);
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) Dft<N1, true>::run(&v[l * N2 + jj * N1]);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, q = s / N;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) {
+        const int l2 = q + N1 * jj;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) lds[(n1 + N1 * l2) * P + kx] = v[l * N2 + jj * N1 + n1];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, m1 = s / N;
+      float2* u = &v[l * N2];
+#pragma unroll
+      for (int l2 = 0; l2 < N2; ++l2) u[l2] = lds[(m1 + N1 * l2) * P + kx];
+#pragma unroll
+      for (int l2 = 1; l2 < N2; ++l2) u[l2] = cmul_conjb(u[l2], tw[m1 * l2]);
+      Dft<N2, true>::run(u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, kx = s % N, m1 = s / N;
+#pragma unroll
+      for (int m2 = 0; m2 < N2; ++m2) lds[(m1 + N1 * m2) * P + kx] = v[l * N2 + m2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, q = s % N1;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) {
+        float2* u = &v[l * N2 + jj * N1];
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) u[k1] = lds[y * P + q + N1 * jj + N2 * k1];
+        Dft<N1, true>::run(u);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, q = s % N1;
+#pragma unroll
+      for (int jj = 0; jj < N2 / N1; ++jj) {
+        const int k2 = q + N1 * jj;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) lds[y * P + sw(n1, k2)] = v[l * N2 + jj * N1 + n1];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int s = t + T * l, y = s / N1, n1 = s % N1;
+      float2* u = &v[l * N2];
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) u[k2] = lds[y * P + sw(n1, k2)];
+#pragma unroll
+      for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul_conjb(u[k2], tw[n1 * k2]);
+      Dft<N2, true>::run(u);
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[n2] = cscale(u[n2], scale);
+    }
+  }
+
+  // Write a layout-A register frame to LDS in natural (y, x) order (pitch P).
+  __device__ __forceinline__ static void store_natural(const float2 (&v)[E], float2* lds) {
+    const int t = opaque_tid();
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int j = 0; j < N2; ++j) lds[a_y(t, l) * P + a_x(t, l, j)] = v[l * N2 + j];
+    __syncthreads();
+  }
+};
+
+// ----------------------------------------------------------------------------- line tiles
+// 1D transforms of NL lines of length N that live in LDS (for frames too large to
+// stay on chip: 256 and 512). Element i of line ln is at lds[ln * LS + i * ES].
+// Each line is served by N1 threads; T threads cover T / N1 lines per round.
+template <int N, int NL, int T>
+struct LineTile {
+  static constexpr int N1 = Split<N>::N1;
+  static constexpr int N2 = Split<N>::N2;
+  static_assert(T % N1 == 0, "");
+  static constexpr int LPR = T / N1;               // lines per round
+  static_assert(NL % LPR == 0, "lines must fill whole rounds");
+  static constexpr int ROUNDS = NL / LPR;
+
+  // In-place transform of all NL lines. Caller syncs before (data in LDS) and after.
+  template <bool INV>
+  __device__ __forceinline__ static void run(float2* lds, int LS, int ES, const float2* __restrict__ tw_) {
+    const int t = opaque_tid();
+    const float2* __restrict__ tw = opaque_ptr(tw_);
+    const int q = t % N1, lr = t / N1;
+    if constexpr (!INV) {
+      // stage 1 in place: x[n1 + N1 n2] -> Y[n1][k2] stored at n1 + N1 k2
+#pragma unroll 1
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+        float2 u[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[(q + N1 * n2) * ES];
+        Dft<N2, false>::run(u);
+#pragma unroll
+        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul(u[k2], tw[q * k2]);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) base[(q + N1 * k2) * ES] = u[k2];
+      }
+      __syncthreads();
+      float2 w[ROUNDS][N2];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+#pragma unroll
+        for (int jj = 0; jj < N2 / N1; ++jj) {
+          const int k2 = q + N1 * jj;
+          float2* u = &w[r][jj * N1];
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1) u[n1] = base[(n1 + N1 * k2) * ES];
+          Dft<N1, false>::run(u);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+#pragma unroll
+        for (int jj = 0; jj < N2 / N1; ++jj)
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) base[(q + N1 * jj + N2 * k1) * ES] = w[r][jj * N1 + k1];
+      }
+    } else {
+      float2 w[ROUNDS][N2];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+#pragma unroll
+        for (int jj = 0; jj < N2 / N1; ++jj) {
+          float2* u = &w[r][jj * N1];
+#pragma unroll
+          for (int k1 = 0; k1 < N1; ++k1) u[k1] = base[(q + N1 * jj + N2 * k1) * ES];
+          Dft<N1, true>::run(u);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+#pragma unroll
+        for (int jj = 0; jj < N2 / N1; ++jj) {
+          const int k2 = q + N1 * jj;
+#pragma unroll
+          for (int n1 = 0; n1 < N1; ++n1) base[(n1 + N1 * k2) * ES] = w[r][jj * N1 + n1];
+        }
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int r = 0; r < ROUNDS; ++r) {
+        float2* base = lds + (lr + LPR * r) * LS;
+        float2 u[N2];
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) u[k2] = base[(q + N1 * k2) * ES];
+#pragma unroll
+        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul_conjb(u[k2], tw[q * k2]);
+        Dft<N2, true>::run(u);
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) base[(q + N1 * n2) * ES] = u[n2];
+      }
+    }
+  }
+};
+
+}  // namespace ptyhip

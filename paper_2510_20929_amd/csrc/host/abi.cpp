@@ -1,0 +1,424 @@
+// Host side of libptyhip: descriptor validation, plans and their workspace, and the
+// orchestration of the fused and per-step forms behind the C ABI of ptyhip.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../../include/ptyhip.h"
+#include "../kernels/launch.hpp"
+#include "plan.hpp"
+
+using namespace ptyhip;
+
+namespace ptyhip {
+
+bool is_supported_frame(int n) {
+  return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512;
+}
+
+// unitary-DFT twiddles W_N^j = exp(-2 pi i j / N), j < N, from double precision
+static std::vector<float2> twiddles(int N) {
+  std::vector<float2> t(N);
+  for (int j = 0; j < N; ++j) {
+    const double a = -2.0 * M_PI * double(j) / double(N);
+    t[j] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  return t;
+}
+
+// exp(-i pi lz (fy^2 + fx^2)) on the unshifted frequency grid (cycles per pixel)
+static std::vector<float2> fresnel(int N, double lz) {
+  std::vector<float2> h(size_t(N) * N);
+  for (int y = 0; y < N; ++y) {
+    const double fy = double(y < (N + 1) / 2 ? y : y - N) / N;
+    for (int x = 0; x < N; ++x) {
+      const double fx = double(x < (N + 1) / 2 ? x : x - N) / N;
+      const double ph = -M_PI * lz * (fy * fy + fx * fx);
+      h[size_t(y) * N + x] = make_float2(float(std::cos(ph)), float(std::sin(ph)));
+    }
+  }
+  return h;
+}
+
+Plan::~Plan() {
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+template <typename T>
+static ptyhip_status dalloc(Plan* p, T** out, size_t n) {
+  *out = nullptr;
+  if (n == 0) return PTYHIP_OK;
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return PTYHIP_ENOMEM;
+  }
+  p->allocs.push_back(ptr);
+  p->bytes += n * sizeof(T);
+  *out = static_cast<T*>(ptr);
+  return PTYHIP_OK;
+}
+
+ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tune* tune) {
+  p->d = d;
+  p->maxK = maxK;
+  if (tune) p->tune = *tune;
+  if (hipGetDevice(&p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return PTYHIP_EHIP;
+  p->cus = prop.multiProcessorCount;
+  const int N = d.frame, M = d.n_modes, E = d.n_eig, S = d.n_slices;
+  const size_t NN = size_t(N) * N;
+  ptyhip_status st;
+
+  std::vector<float2> tw = twiddles(N);
+  if ((st = dalloc(p, &p->tw, size_t(N))) != PTYHIP_OK) return st;
+  if (hipMemcpy(p->tw, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return PTYHIP_EHIP;
+  if (S > 1) {
+    std::vector<float2> h = fresnel(N, double(d.lambda_z));
+    if ((st = dalloc(p, &p->tf, NN)) != PTYHIP_OK) return st;
+    if (hipMemcpy(p->tf, h.data(), NN * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return PTYHIP_EHIP;
+  }
+  if ((st = dalloc(p, &p->flags, 1)) != PTYHIP_OK) return st;
+  if (hipMemset(p->flags, 0, sizeof(uint32_t)) != hipSuccess) return PTYHIP_EHIP;
+  const size_t kk = size_t(std::max(maxK, 1));
+  if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
+  p->copies = p->tune.probe_copies > 0 ? std::min(p->tune.probe_copies, 8) : 8;
+  p->probe_elems = size_t(E) * M * NN;
+  if ((st = dalloc(p, &p->gprobe_part, p->probe_elems * p->copies)) != PTYHIP_OK) return st;
+
+  // fused kernel: on-chip frames up to 128^2, scratch-resident frames above
+  p->on_chip = N <= 128;
+  const int recompute = p->tune.recompute ? 1 : 0;
+  if (p->on_chip) {
+    p->threads = fused_small_threads(N, p->tune.variant);
+    p->scratch_stride = fused_small_scratch_elems(N, S, M, recompute);
+  } else {
+    p->threads = 256;
+    p->scratch_stride = fused_big_scratch_elems(N, S, M);
+  }
+  int grid = p->tune.grid > 0 ? p->tune.grid : p->cus;
+  p->grid = grid;
+  if (p->scratch_stride > 0) {
+    if ((st = dalloc(p, &p->scratch, p->scratch_stride * size_t(grid))) != PTYHIP_OK) return st;
+    p->scratch_bytes = p->scratch_stride * size_t(grid) * sizeof(float2);
+  }
+
+  // per-step path buffers, chunked to a bounded footprint
+  const size_t per_pos = NN * sizeof(float2) * (size_t(S) * 2 + size_t(M) * 2 + (S > 1 ? size_t(S) * M : 0)) +
+                         NN * sizeof(float) + sizeof(int);
+  const size_t budget = size_t(2) << 30;
+  int chunk = p->tune.plain_chunk > 0 ? p->tune.plain_chunk : int(std::max<size_t>(1, budget / per_pos));
+  chunk = std::max(1, std::min(chunk, std::max(maxK, 1)));
+  p->chunk = chunk;
+  const size_t C = size_t(chunk);
+  const size_t before = p->bytes;
+  if ((st = dalloc(p, &p->obuf, size_t(S) * C * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->pbuf, C * M * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->xbuf, C * M * NN)) != PTYHIP_OK) return st;
+  if (S > 1 && (st = dalloc(p, &p->psibuf, size_t(S) * C * M * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->gbuf, size_t(S) * C * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->cbuf, C * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->valid, C)) != PTYHIP_OK) return st;
+  p->plain_bytes = p->bytes - before;
+  return PTYHIP_OK;
+}
+
+ptyhip_status validate_desc(const ptyhip_desc* d) {
+  if (d == nullptr) return PTYHIP_EINVAL;
+  if (!is_supported_frame(d->frame)) return PTYHIP_EUNSUPPORTED;
+  if (d->n_modes < 1 || d->n_modes > 64) return PTYHIP_EINVAL;
+  if (d->n_eig < 1 || d->n_eig > 16) return PTYHIP_EINVAL;
+  if (d->n_slices < 1 || d->n_slices > 64) return PTYHIP_EINVAL;
+  if (d->loss != PTYHIP_LOSS_AMPLITUDE && d->loss != PTYHIP_LOSS_POISSON) return PTYHIP_EUNSUPPORTED;
+  if (d->obj_h < d->frame || d->obj_w < d->frame) return PTYHIP_ESHAPE;
+  if (d->obj_h > (1 << 20) || d->obj_w > (1 << 20)) return PTYHIP_ESHAPE;
+  if (double(d->obj_h) * d->obj_w * d->n_slices > 4.0e9) return PTYHIP_ESHAPE;
+  if (!std::isfinite(d->poisson_eps) || d->poisson_eps < 0.f) return PTYHIP_ENONFINITE;
+  if (!std::isfinite(d->lambda_z)) return PTYHIP_ENONFINITE;
+  if (!std::isfinite(d->norm_count)) return PTYHIP_ENONFINITE;
+  if (d->n_slices > 1 && d->frame > 128) return PTYHIP_EUNSUPPORTED;
+  return PTYHIP_OK;
+}
+
+// Build the kernel argument block of one call.
+static CallArgs make_args(const Plan* p, int K, int mode, uint32_t flags, const float* obj, const float* probe,
+                          const float* weights, const float* positions, const float* I_meas, const float* Y,
+                          float* Psi, float* I_pred, float* g_obj, bool want_probe, bool want_pos, bool want_w) {
+  const ptyhip_desc& d = p->d;
+  CallArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.obj = reinterpret_cast<const float2*>(obj);
+  a.probe = reinterpret_cast<const float2*>(probe);
+  a.weights = weights;
+  a.pos = positions;
+  a.imeas = I_meas;
+  a.Y = reinterpret_cast<const float2*>(Y);
+  a.psi_out = reinterpret_cast<float2*>(Psi);
+  a.ipred = I_pred;
+  a.gobj = reinterpret_cast<float2*>(g_obj);
+  a.gprobe = want_probe ? p->gprobe_part : nullptr;
+  a.gprobe_copies = p->copies;
+  a.loss_part = p->loss_part;
+  a.pos_part = want_pos ? p->pos_part : nullptr;
+  a.w_part = want_w ? p->w_part : nullptr;
+  a.flags = p->flags;
+  a.tw = p->tw;
+  a.tf = p->tf;
+  a.scratch = p->scratch;
+  a.scratch_stride = p->scratch_stride;
+  a.K = K;
+  a.H = d.obj_h;
+  a.W = d.obj_w;
+  a.M = d.n_modes;
+  a.E = d.n_eig;
+  a.S = d.n_slices;
+  a.loss = d.loss;
+  a.eps = d.poisson_eps;
+  const double kn = d.norm_count > 0.0 ? d.norm_count : double(std::max(K, 1));
+  const double nn = double(d.frame) * d.frame;
+  a.gscale = float(2.0 / (kn * nn));
+  a.lscale = float(1.0 / (kn * nn));
+  a.want = (g_obj ? WANT_OBJ : 0) | (want_probe ? WANT_PROBE : 0) | (want_pos ? WANT_POS : 0) |
+           (want_w ? WANT_WEIGHTS : 0) | (I_pred ? WANT_IPRED : 0);
+  a.mode = mode;
+  a.recompute = p->tune.recompute ? 1 : 0;
+  (void)flags;
+  return a;
+}
+
+// Launch the chosen form over K positions (the plain form runs chunk by chunk).
+static ptyhip_status run_core(Plan* p, const CallArgs& a, bool plain, hipStream_t st) {
+  if (a.K == 0) return PTYHIP_OK;
+  const int N = p->d.frame;
+  if (!plain && (p->on_chip || p->big_fused_ready)) {
+    hipError_t e = p->on_chip ? launch_fused_small(a, N, p->tune.variant, p->grid, st)
+                              : launch_fused_big(a, N, p->grid, st);
+    return e == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
+  }
+  for (int k0 = 0; k0 < a.K; k0 += p->chunk) {
+    PlainArgs b;
+    b.a = a;
+    b.N = N;
+    b.C = std::min(p->chunk, a.K - k0);
+    b.k0 = k0;
+    b.obuf = p->obuf;
+    b.pbuf = p->pbuf;
+    b.xbuf = p->xbuf;
+    b.psibuf = p->psibuf;
+    b.gbuf = p->gbuf;
+    b.cbuf = p->cbuf;
+    b.valid = p->valid;
+    hipError_t e = run_plain_chunk(b, st);
+    if (e == hipErrorNotSupported) return PTYHIP_EUNSUPPORTED;
+    if (e != hipSuccess) return PTYHIP_EHIP;
+  }
+  return PTYHIP_OK;
+}
+
+ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
+                                   const float* probe, const float* weights, const float* positions,
+                                   const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,
+                                   float* g_pos, float* g_weights, bool forward_only) {
+  if (p == nullptr) return PTYHIP_EINVAL;
+  if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
+  const ptyhip_desc& d = p->d;
+  if (!obj || !probe || !positions || !I_meas || !loss) return PTYHIP_EINVAL;
+  if (d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  const bool want_obj = !forward_only && (flags & PTYHIP_GRAD_OBJ);
+  const bool want_probe = !forward_only && (flags & PTYHIP_GRAD_PROBE);
+  const bool want_pos = !forward_only && (flags & PTYHIP_GRAD_POS);
+  const bool want_w = !forward_only && (flags & PTYHIP_GRAD_WEIGHTS);
+  if (want_obj && !g_obj) return PTYHIP_EINVAL;
+  if (want_probe && !g_probe) return PTYHIP_EINVAL;
+  if (want_pos && !g_pos) return PTYHIP_EINVAL;
+  if (want_w && (!g_weights || !weights)) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  const bool acc = (flags & PTYHIP_ACCUMULATE) != 0;
+  const bool any_grad = want_obj || want_probe || want_pos || want_w;
+  const int mode = (forward_only || !any_grad) ? MODE_FORWARD : MODE_FWD_ADJ;
+  CallArgs a = make_args(p, K, mode, flags, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
+                         want_obj ? g_obj : nullptr, want_probe, want_pos, want_w);
+  const size_t obj_floats = size_t(d.n_slices) * d.obj_h * d.obj_w * 2;
+  if (want_obj && !acc && launch_fill(g_obj, obj_floats, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+  if (want_probe &&
+      launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
+    return PTYHIP_EHIP;
+  ptyhip_status s = run_core(p, a, (flags & PTYHIP_PLAIN) != 0, st);
+  if (s != PTYHIP_OK) return s;
+  FinalArgs f;
+  std::memset(&f, 0, sizeof(f));
+  f.loss_part = p->loss_part;
+  f.loss = loss;
+  f.pos_part = p->pos_part;
+  f.g_pos = want_pos ? g_pos : nullptr;
+  f.w_part = p->w_part;
+  f.g_w = want_w ? g_weights : nullptr;
+  f.gprobe_part = p->gprobe_part;
+  f.g_probe = want_probe ? reinterpret_cast<float2*>(g_probe) : nullptr;
+  f.copies = p->copies;
+  f.probe_elems = p->probe_elems;
+  f.K = K;
+  f.E = d.n_eig;
+  f.accumulate = acc ? 1 : 0;
+  return launch_finalize(f, st) == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
+}
+
+}  // namespace ptyhip
+
+// ============================================================================= C ABI
+extern "C" {
+
+const char* ptyhip_status_str(ptyhip_status s) {
+  switch (s) {
+    case PTYHIP_OK: return "ok";
+    case PTYHIP_EINVAL: return "invalid argument (NULL pointer or bad value)";
+    case PTYHIP_ESHAPE: return "inconsistent shape";
+    case PTYHIP_EBOUNDS: return "position count outside [0, max_positions]";
+    case PTYHIP_ENONFINITE: return "non-finite parameter";
+    case PTYHIP_EHIP: return "HIP runtime error";
+    case PTYHIP_ENOMEM: return "device allocation failed";
+    case PTYHIP_EUNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+const char* ptyhip_version(void) { return "ptyhip 0.1 (gfx950)"; }
+
+ptyhip_status ptyhip_desc_validate(const ptyhip_desc* desc) { return validate_desc(desc); }
+
+ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positions, const ptyhip_tune* tune,
+                                    ptyhip_plan* out) {
+  if (out == nullptr) return PTYHIP_EINVAL;
+  *out = nullptr;
+  ptyhip_status s = validate_desc(desc);
+  if (s != PTYHIP_OK) return s;
+  if (max_positions < 0) return PTYHIP_EBOUNDS;
+  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 || tune->probe_copies < 0 ||
+               tune->plain_chunk < 0 || tune->recompute < 0))
+    return PTYHIP_EINVAL;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return PTYHIP_ENOMEM;
+  s = plan_init(p, *desc, max_positions, tune);
+  if (s != PTYHIP_OK) {
+    delete p;
+    return s;
+  }
+  *out = reinterpret_cast<ptyhip_plan>(p);
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_plan_create(const ptyhip_desc* desc, int32_t max_positions, ptyhip_plan* out) {
+  return ptyhip_plan_create_ex(desc, max_positions, nullptr, out);
+}
+
+void ptyhip_plan_destroy(ptyhip_plan plan) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  delete p;
+}
+
+ptyhip_status ptyhip_plan_get_info(ptyhip_plan plan, ptyhip_plan_info* info) {
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!p || !info) return PTYHIP_EINVAL;
+  info->workspace_bytes = p->bytes;
+  info->scratch_bytes = p->scratch_bytes;
+  info->plain_bytes = p->plain_bytes;
+  info->grid = p->grid;
+  info->threads = p->threads;
+  info->fused_on_chip = p->on_chip ? 1 : 0;
+  info->plain_chunk = p->chunk;
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_forward(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,
+                             const float* weights, const float* positions, const float* I_meas, double* loss,
+                             float* I_pred) {
+  return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K, 0, obj, probe,
+                              weights, positions, I_meas, loss, I_pred, nullptr, nullptr, nullptr, nullptr, true);
+}
+
+ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
+                                     const float* probe, const float* weights, const float* positions,
+                                     const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                     float* g_probe, float* g_pos, float* g_weights) {
+  return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K, flags, obj, probe,
+                              weights, positions, I_meas, loss, I_pred, g_obj, g_probe, g_pos, g_weights, false);
+}
+
+ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,
+                             const float* weights, const float* positions, float* Psi) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
+  if (!obj || !probe || !positions || !Psi) return PTYHIP_EINVAL;
+  if (p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CallArgs a = make_args(p, K, MODE_APPLY_A, 0, obj, probe, weights, positions, nullptr, nullptr, Psi, nullptr,
+                         nullptr, false, false, false);
+  return run_core(p, a, false, st);
+}
+
+ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const float* Y, const float* obj,
+                              const float* probe, const float* weights, const float* positions, float* g_obj,
+                              float* g_probe) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
+  if (!Y || !obj || !probe || !positions) return PTYHIP_EINVAL;
+  if (p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ptyhip_desc& d = p->d;
+  CallArgs a = make_args(p, K, MODE_APPLY_AH, 0, obj, probe, weights, positions, nullptr, Y, nullptr, nullptr,
+                         g_obj, g_probe != nullptr, false, false);
+  if (g_obj && launch_fill(g_obj, size_t(d.n_slices) * d.obj_h * d.obj_w * 2, 0.f, st) != hipSuccess)
+    return PTYHIP_EHIP;
+  if (g_probe &&
+      launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
+    return PTYHIP_EHIP;
+  ptyhip_status s = run_core(p, a, false, st);
+  if (s != PTYHIP_OK) return s;
+  if (g_probe) {
+    FinalArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.gprobe_part = p->gprobe_part;
+    f.g_probe = reinterpret_cast<float2*>(g_probe);
+    f.copies = p->copies;
+    f.probe_elems = p->probe_elems;
+    f.K = K;
+    f.E = d.n_eig;
+    if (launch_finalize(f, st) != hipSuccess) return PTYHIP_EHIP;
+  }
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !flags) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return PTYHIP_EHIP;
+  if (hipMemcpy(flags, p->flags, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return PTYHIP_EHIP;
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  return launch_fill(reinterpret_cast<float*>(p->flags), 1, 0.f, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? PTYHIP_OK
+             : PTYHIP_EHIP;
+}
+
+}  // extern "C"

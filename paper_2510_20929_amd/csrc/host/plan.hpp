@@ -1,0 +1,61 @@
+// Plan object behind ptyhip_plan: the problem description, the implementation choices
+// and every device buffer the plan owns.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../../include/ptyhip.h"
+#include "../kernels/args.hpp"
+
+namespace ptyhip {
+
+struct Plan {
+  ptyhip_desc d{};
+  ptyhip_tune tune{};
+  int maxK = 0;
+  int device = 0;
+  int cus = 0;
+  // fused form
+  bool on_chip = true;
+  bool big_fused_ready = false;
+  int threads = 0;
+  int grid = 0;
+  int copies = 8;
+  // tables and per-call partials
+  float2* tw = nullptr;
+  float2* tf = nullptr;
+  uint32_t* flags = nullptr;
+  double* loss_part = nullptr;
+  double* pos_part = nullptr;
+  double* w_part = nullptr;
+  float2* gprobe_part = nullptr;
+  size_t probe_elems = 0;
+  float2* scratch = nullptr;
+  size_t scratch_stride = 0;
+  size_t scratch_bytes = 0;
+  // per-step form
+  int chunk = 0;
+  float2* obuf = nullptr;
+  float2* pbuf = nullptr;
+  float2* xbuf = nullptr;
+  float2* psibuf = nullptr;
+  float2* gbuf = nullptr;
+  float* cbuf = nullptr;
+  int* valid = nullptr;
+  size_t plain_bytes = 0;
+  // bookkeeping
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  ~Plan();
+};
+
+bool is_supported_frame(int n);
+ptyhip_status validate_desc(const ptyhip_desc* d);
+ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tune* tune);
+ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
+                                   const float* probe, const float* weights, const float* positions,
+                                   const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,
+                                   float* g_pos, float* g_weights, bool forward_only);
+
+}  // namespace ptyhip

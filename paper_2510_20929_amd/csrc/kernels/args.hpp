@@ -1,0 +1,53 @@
+// Argument block of one forward / forward-adjoint / apply_A / apply_AH call, as the
+// kernels see it. Built by the host library from the plan and the caller's pointers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptyhip {
+
+enum CallMode : int { MODE_FORWARD = 0, MODE_FWD_ADJ = 1, MODE_APPLY_A = 2, MODE_APPLY_AH = 3 };
+
+enum WantBits : int {
+  WANT_OBJ = 1,
+  WANT_PROBE = 2,
+  WANT_POS = 4,
+  WANT_WEIGHTS = 8,
+  WANT_IPRED = 16,
+};
+
+struct CallArgs {
+  // inputs (device)
+  const float2* obj;      // [S][H][W]
+  const float2* probe;    // [E][M][N][N]
+  const float* weights;   // [K][E] or nullptr (then E == 1 and w == 1)
+  const float* pos;       // [K][2] (y, x) frame top-left, object pixels
+  const float* imeas;     // [K][N][N] DC-centred
+  const float2* Y;        // apply_AH input [K][M][N][N] (unshifted) or nullptr
+  // outputs (device)
+  float2* psi_out;        // apply_A output [K][M][N][N] (unshifted)
+  float* ipred;           // [K][N][N] DC-centred, or nullptr
+  float2* gobj;           // [S][H][W], accumulated with atomics, or nullptr
+  float2* gprobe;         // [NCOPY][E][M][N][N] workspace partials, or nullptr
+  int gprobe_copies;      // NCOPY (per-XCD copies)
+  double* loss_part;      // [K] per-position loss (already normalised)
+  double* pos_part;       // [K][2]
+  double* w_part;         // [K][E]
+  uint32_t* flags;        // device error latch
+  // tables and workspace
+  const float2* tw;       // W_N^j, j in [0, N)
+  const float2* tf;       // Fresnel transfer function [N][N] (unshifted), S > 1
+  float2* scratch;        // per-workgroup scratch base
+  size_t scratch_stride;  // float2 elements per workgroup
+  // sizes
+  int K, H, W, M, E, S;
+  int loss;               // 0 amplitude, 1 Poisson
+  float eps;              // Poisson regulariser
+  float gscale;           // 2 / (Knorm N^2)
+  float lscale;           // 1 / (Knorm N^2)
+  int want;               // WantBits
+  int mode;               // CallMode
+  int recompute;          // multislice: recompute incident waves instead of storing them
+};
+
+}  // namespace ptyhip

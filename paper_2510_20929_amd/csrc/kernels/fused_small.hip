@@ -1,0 +1,515 @@
+// Fused forward + adjoint for frames that stay on chip (N <= 128).
+//
+// One workgroup owns one scan position at a time (positions are strided over a
+// persistent grid, so the workgroups in flight cover a compact stretch of the scan
+// and share object rows in L2). For each position it
+//   gathers the bilinear object patch (registers),
+//   forms each mode's exit wave, transforms it (registers + LDS), sums |Psi|^2,
+//   evaluates the loss against the measured pattern and dl/dI,
+//   scales each mode's far field by 2 dl/dI / (K_norm N^2) and transforms back,
+//   forms the patch gradient sum_m conj(P_m) g_m and the probe gradient conj(o) g_m,
+//   and finally builds the (N+1)^2 object-window gradient in LDS from the patch
+//   gradient (the transpose of the bilinear gather), adding it to the object
+//   gradient with one atomic per window pixel, while the same pass reduces the
+//   position gradient.
+// Multislice: incident waves and patches of every slice live in a per-workgroup
+// scratch area (L2/MALL resident), or the incident waves are recomputed.
+#include "../device/fft.hpp"
+#include "../device/model.hpp"
+#include "launch.hpp"
+
+namespace ptyhip {
+
+constexpr int MAX_EIG = 16;
+
+template <int N, int T>
+struct SmallCtx {
+  using F = Frame2D<N, T>;
+  static constexpr int E = F::E;
+  static constexpr int L = F::L;
+  static constexpr int N2 = F::N2;
+  static constexpr int NN = N * N;
+  __device__ __forceinline__ static int a_pix(int t, int i) {
+    const int l = i / N2, j = i % N2;
+    return F::a_y(t, l) * N + F::a_x(t, l, j);
+  }
+  __device__ __forceinline__ static int d_freq(int t, int i) {
+    const int l = i / N2, ii = i % N2;
+    return F::d_ky(t, l, ii) * N + F::d_kx(t, l);
+  }
+  __device__ __forceinline__ static int d_centred(int t, int i) {
+    const int l = i / N2, ii = i % N2;
+    return centred_index(F::d_ky(t, l, ii), F::d_kx(t, l), N);
+  }
+};
+
+// Zero every per-position output of an invalid position and latch the error.
+template <int N, int T>
+__device__ __forceinline__ void skip_position(const CallArgs& a, int k, const PosInfo& p) {
+  constexpr int NN = N * N;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
+    if (a.loss_part) a.loss_part[k] = 0.0;
+    if (a.pos_part) {
+      a.pos_part[2 * k] = 0.0;
+      a.pos_part[2 * k + 1] = 0.0;
+    }
+  }
+  if (a.w_part && tid < a.E) a.w_part[size_t(k) * a.E + tid] = 0.0;
+  if (a.ipred)
+    for (int i = tid; i < NN; i += T) a.ipred[size_t(k) * NN + i] = 0.f;
+  if (a.mode == MODE_APPLY_A)
+    for (int i = tid; i < a.M * NN; i += T) a.psi_out[size_t(k) * a.M * NN + i] = make_float2(0.f, 0.f);
+}
+
+// Loss of one position from the incoherent sum held in layout D; on return Iacc holds
+// dl/dI. Returns false if the position's loss is not finite (then it is skipped).
+template <int N, int T, int LOSS>
+__device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&Iacc)[Frame2D<N, T>::E],
+                                              double* red) {
+  using C = SmallCtx<N, T>;
+  const float* im = a.imeas + size_t(k) * C::NN;
+  const int t = opaque_tid();
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < C::E; ++i) {
+    const int ci = C::d_centred(t, i);
+    float l, c;
+    loss_terms<LOSS>(Iacc[i], im[ci], a.eps, l, c);
+    if (a.ipred) a.ipred[size_t(k) * C::NN + ci] = Iacc[i];
+    lsum += double(l);
+    Iacc[i] = c;
+  }
+  const double tot = block_sum<T>(lsum, red);
+  const bool fin = isfinite(tot);
+  if (threadIdx.x == 0) {
+    a.loss_part[k] = fin ? tot * double(a.lscale) : 0.0;
+    if (!fin) latch(a.flags, FLAG_NONFINITE);
+  }
+  return fin;
+}
+
+// Probe-side gradients of one mode from the gradient g of the incident probe wave
+// (layout A): atomics into the probe partials and the OPR weight-gradient sums.
+template <int N, int T>
+__device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m, const float* wk,
+                                                const float2 (&gP)[Frame2D<N, T>::E], double* red,
+                                                double* wacc) {
+  using C = SmallCtx<N, T>;
+  const int t = opaque_tid();
+  if ((a.want & WANT_PROBE) && a.gprobe) {
+    float2* gp = a.gprobe + size_t(blockIdx.x % a.gprobe_copies) * a.E * a.M * C::NN;
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) {
+      const int pix = C::a_pix(t, i);
+      if (wk == nullptr) {
+        atomic_add_c(gp + size_t(m) * C::NN + pix, gP[i]);
+      } else {
+        for (int e = 0; e < a.E; ++e) atomic_add_c(gp + (size_t(e) * a.M + m) * C::NN + pix, cscale(gP[i], wk[e]));
+      }
+    }
+  }
+  if ((a.want & WANT_WEIGHTS) && wk != nullptr) {
+    for (int e = 0; e < a.E; ++e) {
+      const float2* U = a.probe + (size_t(e) * a.M + m) * C::NN;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) s += double(cdotre(gP[i], U[C::a_pix(t, i)]));
+      s = block_sum<T>(s, red);
+      if (threadIdx.x == 0) wacc[e] += s;
+    }
+  }
+}
+
+// Object-window pass for one slice: LDS holds the patch gradient in natural order.
+// Adds the bilinear-transposed window into gobj and accumulates the position gradient.
+template <int N, int T>
+__device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p, const float2* lds,
+                                           const float2* __restrict__ Os, float2* gOs, double& gy, double& gx) {
+  constexpr int P = Frame2D<N, T>::P;
+  const int WH = N + p.ey, WW = N + p.ex;
+  const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
+  const float w10 = p.fy * (1.f - p.fx), w11 = p.fy * p.fx;
+  const bool want_obj = (a.want & WANT_OBJ) && gOs != nullptr;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const float2 z = make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < WH * WW; idx += T) {
+    const int py = idx / WW, px = idx - py * WW;
+    const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
+    const float2 g00 = (iy0 && ix0) ? lds[py * P + px] : z;
+    const float2 g01 = (iy0 && ix1) ? lds[py * P + px - 1] : z;
+    const float2 g10 = (iy1 && ix0) ? lds[(py - 1) * P + px] : z;
+    const float2 g11 = (iy1 && ix1) ? lds[(py - 1) * P + px - 1] : z;
+    const size_t oi = size_t(p.y0 + py) * a.W + (p.x0 + px);
+    if (want_obj) {
+      float2 g;
+      g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
+      g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
+      atomic_add_c(gOs + oi, g);
+    }
+    if (want_pos) {
+      const float2 A = Os[oi];
+      float2 hy, hx;
+      hy.x = (1.f - p.fx) * (g10.x - g00.x) + p.fx * (g11.x - g01.x);
+      hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
+      hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
+      hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
+      gy += double(cdotre(hy, A));
+      gx += double(cdotre(hx, A));
+    }
+  }
+}
+
+template <int N, int T>
+__device__ __forceinline__ void finish_position(const CallArgs& a, int k, double gy, double gx, double* red,
+                                                const double* wacc) {
+  if ((a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && a.pos_part) {
+    double v[2] = {gy, gx};
+    block_sum_n<T, 2>(v, red);
+    if (threadIdx.x == 0) {
+      a.pos_part[2 * k] = v[0];
+      a.pos_part[2 * k + 1] = v[1];
+    }
+  }
+  if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights) {
+    __syncthreads();
+    if (int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = wacc[threadIdx.x];
+  }
+}
+
+// ----------------------------------------------------------------------------- single slice
+// Registers hold only the working frame v and dl/dI (3 E floats per thread). The patch
+// o and, with several modes, the running patch gradient sum_m conj(P_m) g_m live in
+// the workgroup's scratch frames ([E][T], coalesced, L2 resident); the finished patch
+// gradient goes straight to LDS on the last mode.
+template <int N, int T, int LOSS>
+__global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
+  using F = Frame2D<N, T>;
+  using C = SmallCtx<N, T>;
+  constexpr int E = C::E;
+  __shared__ float2 lds[F::LDS_ELEMS];
+  __shared__ double red[2 * (T / WAVE)];
+  __shared__ float wsh[MAX_EIG];
+  __shared__ double wacc[MAX_EIG];
+  const float inv_n = 1.f / float(N);
+  const bool fwd = a.mode != MODE_APPLY_AH;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  float2* obuf = a.scratch + size_t(blockIdx.x) * a.scratch_stride;
+  float2* gacc = obuf + size_t(C::NN);
+
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) {
+      skip_position<N, T>(a, k, p);
+      continue;
+    }
+    __syncthreads();
+    if (a.weights && int(threadIdx.x) < a.E) wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
+    if (threadIdx.x < MAX_EIG) wacc[threadIdx.x] = 0.0;
+    __syncthreads();
+    const float* wk = a.weights ? wsh : nullptr;
+
+    {
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = i / C::N2, j = i % C::N2;
+        obuf[size_t(i) * T + t] = bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
+      }
+    }
+
+    float2 v[E];
+    float cf[E];
+    if (fwd) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cf[i] = 0.f;
+      for (int m = 0; m < a.M; ++m) {
+        {
+          const int t = opaque_tid();
+#pragma unroll
+          for (int i = 0; i < E; ++i)
+            v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+        }
+        F::forward(v, lds, a.tw, inv_n);
+#pragma unroll
+        for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
+        if (a.mode == MODE_APPLY_A) {
+          const int t = opaque_tid();
+          float2* out = a.psi_out + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+          for (int i = 0; i < E; ++i) out[C::d_freq(t, i)] = v[i];
+        }
+      }
+      if (a.mode == MODE_APPLY_A) continue;
+      if (!position_loss<N, T, LOSS>(a, k, cf, red)) continue;
+      if (a.mode == MODE_FORWARD) continue;
+    }
+
+    for (int m = 0; m < a.M; ++m) {
+      if (!fwd) {
+        const int t = opaque_tid();
+        const float2* y = a.Y + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = y[C::d_freq(t, i)];
+      } else {
+        if (a.M > 1) {
+          const int t = opaque_tid();
+#pragma unroll
+          for (int i = 0; i < E; ++i)
+            v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+          F::forward(v, lds, a.tw, inv_n);
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
+      }
+      F::inverse(v, lds, a.tw, inv_n);
+      const bool last = m == a.M - 1;
+      __syncthreads();  // every thread is done reading LDS before the patch gradient lands there
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int pix = C::a_pix(t, i);
+          float2 go = cmulc(probe_at(a.probe, wk, a.E, a.M, C::NN, m, pix), v[i]);
+          const size_t si = size_t(i) * T + t;
+          if (m > 0) go = cadd(go, gacc[si]);
+          if (last) lds[(pix / N) * F::P + (pix % N)] = go;
+          else gacc[si] = go;
+          v[i] = cmulc(obuf[si], v[i]);
+        }
+      }
+      probe_gradients<N, T>(a, k, m, wk, v, red, wacc);
+    }
+
+    __syncthreads();
+    double gy = 0.0, gx = 0.0;
+    window_pass<N, T>(a, p, lds, a.obj, a.gobj, gy, gx);
+    finish_position<N, T>(a, k, gy, gx, red, wacc);
+  }
+}
+
+// ----------------------------------------------------------------------------- multislice
+// Scratch per workgroup (float2 elements, element i of thread t at i*T + t):
+//   patches [S][E*T], incident waves [M][S][E*T] (unless recomputed), patch gradients [S][E*T]
+template <int N, int T, int LOSS>
+__global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
+  using F = Frame2D<N, T>;
+  using C = SmallCtx<N, T>;
+  constexpr int E = C::E;
+  constexpr size_t FR = size_t(E) * T;  // one frame in scratch
+  __shared__ float2 lds[F::LDS_ELEMS];
+  __shared__ double red[2 * (T / WAVE)];
+  __shared__ float wsh[MAX_EIG];
+  __shared__ double wacc[MAX_EIG];
+  const int tid = threadIdx.x;
+  const int S = a.S;
+  const float inv_n = 1.f / float(N);
+  const bool fwd = a.mode != MODE_APPLY_AH;
+  const bool recompute = a.recompute || !fwd;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  float2* scr = a.scratch + size_t(blockIdx.x) * a.scratch_stride;
+  float2* Op = scr;                                   // [S][FR]
+  float2* Gp = Op + size_t(S) * FR;                   // [S][FR]
+  float2* Ps = Gp + size_t(S) * FR;                   // [M][S][FR]
+  const size_t HW = size_t(a.H) * a.W;
+
+  // multiply by the slice transfer function (or its conjugate) in layout D
+  auto apply_tf = [&](float2 (&v)[E], bool conj) {
+    const int t = opaque_tid();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const float2 h = a.tf[C::d_freq(t, i)];
+      v[i] = conj ? cmulc(h, v[i]) : cmul(h, v[i]);
+    }
+  };
+  // incident wave of mode m at slice s (layout A), starting from the probe
+  auto incident = [&](float2 (&v)[E], int m, int s, const float* wk) {
+    {
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i));
+    }
+    for (int u = 0; u < s; ++u) {
+      const float2* o = Op + size_t(u) * FR;
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
+      F::forward(v, lds, a.tw, inv_n);
+      apply_tf(v, false);
+      F::inverse(v, lds, a.tw, inv_n);
+    }
+  };
+
+  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) {
+      skip_position<N, T>(a, k, p);
+      continue;
+    }
+    __syncthreads();
+    if (a.weights && tid < a.E) wsh[tid] = a.weights[size_t(k) * a.E + tid];
+    if (tid < MAX_EIG) wacc[tid] = 0.0;
+    __syncthreads();
+    const float* wk = a.weights ? wsh : nullptr;
+
+    for (int s = 0; s < S; ++s) {
+      float2* o = Op + size_t(s) * FR;
+      float2* g = Gp + size_t(s) * FR;
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = i / C::N2, j = i % C::N2;
+        o[size_t(i) * T + t] = bilinear(a.obj + size_t(s) * HW, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
+        g[size_t(i) * T + t] = make_float2(0.f, 0.f);
+      }
+    }
+
+    float2 v[E];
+    float cf[E];
+    if (fwd) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cf[i] = 0.f;
+      for (int m = 0; m < a.M; ++m) {
+        {
+          const int t = opaque_tid();
+#pragma unroll
+          for (int i = 0; i < E; ++i) v[i] = probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i));
+        }
+        for (int s = 0; s < S; ++s) {
+          const float2* o = Op + size_t(s) * FR;
+          const int t = opaque_tid();
+          if (!recompute) {
+            float2* ps = Ps + (size_t(m) * S + s) * FR;
+#pragma unroll
+            for (int i = 0; i < E; ++i) ps[size_t(i) * T + t] = v[i];
+          }
+#pragma unroll
+          for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
+          F::forward(v, lds, a.tw, inv_n);
+          if (s < S - 1) {
+            apply_tf(v, false);
+            F::inverse(v, lds, a.tw, inv_n);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
+        if (a.mode == MODE_APPLY_A) {
+          const int t = opaque_tid();
+          float2* out = a.psi_out + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+          for (int i = 0; i < E; ++i) out[C::d_freq(t, i)] = v[i];
+        }
+      }
+      if (a.mode == MODE_APPLY_A) continue;
+      if (!position_loss<N, T, LOSS>(a, k, cf, red)) continue;
+      if (a.mode == MODE_FORWARD) continue;
+    }
+
+    for (int m = 0; m < a.M; ++m) {
+      if (!fwd) {
+        const int t = opaque_tid();
+        const float2* y = a.Y + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = y[C::d_freq(t, i)];
+      } else {
+        if (!recompute) {
+          const int t = opaque_tid();
+          const float2* ps = Ps + (size_t(m) * S + (S - 1)) * FR;
+#pragma unroll
+          for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
+        } else {
+          incident(v, m, S - 1, wk);
+        }
+        const float2* o = Op + size_t(S - 1) * FR;
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
+        F::forward(v, lds, a.tw, inv_n);
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
+      }
+      F::inverse(v, lds, a.tw, inv_n);
+      for (int s = S - 1; s >= 0; --s) {
+        float2 ps[E];
+        if (!recompute) {
+          const int t = opaque_tid();
+          const float2* src = Ps + (size_t(m) * S + s) * FR;
+#pragma unroll
+          for (int i = 0; i < E; ++i) ps[i] = src[size_t(i) * T + t];
+        } else {
+          incident(ps, m, s, wk);
+        }
+        const float2* o = Op + size_t(s) * FR;
+        float2* g = Gp + size_t(s) * FR;
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const size_t si = size_t(i) * T + t;
+          g[si] = cadd(g[si], cmulc(ps[i], v[i]));
+          v[i] = cmulc(o[si], v[i]);
+        }
+        if (s > 0) {
+          F::forward(v, lds, a.tw, inv_n);
+          apply_tf(v, true);
+          F::inverse(v, lds, a.tw, inv_n);
+        }
+      }
+      probe_gradients<N, T>(a, k, m, wk, v, red, wacc);
+    }
+
+    double gy = 0.0, gx = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const float2* g = Gp + size_t(s) * FR;
+      const int t = opaque_tid();
+      float2 go[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) go[i] = g[size_t(i) * T + t];
+      F::store_natural(go, lds);
+      window_pass<N, T>(a, p, lds, a.obj + size_t(s) * HW, a.gobj ? a.gobj + size_t(s) * HW : nullptr, gy, gx);
+    }
+    finish_position<N, T>(a, k, gy, gx, red, wacc);
+  }
+}
+
+// ----------------------------------------------------------------------------- launchers
+template <int N, int T>
+static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
+  const bool ms = a.S > 1;
+  if (a.loss == 0) {
+    if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
+  } else {
+    if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+int fused_small_threads(int N, int variant) {
+  switch (N) {
+    case 16: return 64;
+    case 32: return 128;
+    case 64: return variant == 1 ? 256 : 512;
+    case 128: return variant == 1 ? 1024 : 512;
+    default: return 0;
+  }
+}
+
+size_t fused_small_scratch_elems(int N, int S, int M, int recompute) {
+  const size_t fr = size_t(N) * N;
+  if (S <= 1) return fr * (M > 1 ? 2 : 1);
+  return fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+}
+
+hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st) {
+  switch (N) {
+    case 16: return launch_small_t<16, 64>(a, grid, st);
+    case 32: return launch_small_t<32, 128>(a, grid, st);
+    case 64: return variant == 1 ? launch_small_t<64, 256>(a, grid, st) : launch_small_t<64, 512>(a, grid, st);
+    case 128: return variant == 1 ? launch_small_t<128, 1024>(a, grid, st) : launch_small_t<128, 512>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ptyhip

@@ -1,0 +1,51 @@
+// Host-side launchers of the ptyhip kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include "args.hpp"
+
+namespace ptyhip {
+
+// Working buffers of one chunk of the plain (per-step) path.
+struct PlainArgs {
+  CallArgs a;
+  int N, C, k0;
+  float2* obuf;    // [S][C][N*N]   patches
+  float2* pbuf;    // [C][M][N*N]   per-position probes (weighted)
+  float2* xbuf;    // [C][M][N*N]   exit / far-field waves
+  float2* psibuf;  // [S][C][M][N*N] incident waves (multislice)
+  float2* gbuf;    // [S][C][N*N]   patch gradients
+  float* cbuf;     // [C][N*N]      dl/dI
+  int* valid;      // [C]
+};
+
+// Final reductions of one call.
+struct FinalArgs {
+  const double* loss_part;  // [K]
+  double* loss;             // device scalar or nullptr
+  const double* pos_part;   // [K][2] or nullptr
+  float* g_pos;             // [K][2] or nullptr
+  const double* w_part;     // [K][E] or nullptr
+  float* g_w;               // [K][E] or nullptr
+  const float2* gprobe_part;  // [copies][E*M*N*N] or nullptr
+  float2* g_probe;          // [E*M*N*N] or nullptr
+  int copies;
+  size_t probe_elems;
+  int K, E;
+  int accumulate;
+};
+
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st);
+hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inverse, hipStream_t st);
+hipError_t run_plain_chunk(PlainArgs b, hipStream_t st);
+
+int fused_small_threads(int N, int variant);
+size_t fused_small_scratch_elems(int N, int S, int M, int recompute);
+hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
+
+size_t fused_big_scratch_elems(int N, int S, int M);
+hipError_t launch_fused_big(const CallArgs& a, int N, int grid, hipStream_t st);
+
+hipError_t launch_finalize(const FinalArgs& f, hipStream_t st);
+
+}  // namespace ptyhip

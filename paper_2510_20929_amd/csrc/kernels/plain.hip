@@ -1,0 +1,427 @@
+// The "plain" form of the forward/adjoint: one small kernel per step, each reading
+// and writing its operands in HBM (patch gather, probe synthesis, exit wave, 2D FFT,
+// intensity and loss, residual, inverse FFT, conjugate multiplies, probe reduction,
+// naive bilinear scatter with global atomics, position gradient). It computes the
+// same quantities as the fused kernels from the same device helpers, and is the
+// baseline the fused form is measured against.
+#include "../device/fft.hpp"
+#include "../device/model.hpp"
+#include "launch.hpp"
+
+namespace ptyhip {
+
+// ----------------------------------------------------------------------------- utilities
+__global__ void fill_f32_kernel(float* p, size_t n, float v) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st) {
+  if (n == 0 || p == nullptr) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- FFT of whole frames
+template <int N, int T, bool INV>
+__global__ __launch_bounds__(T) void fft_frames_kernel(float2* X, int nframes, const float2* __restrict__ tw,
+                                                       float scale) {
+  using F = Frame2D<N, T>;
+  constexpr int E = F::E, N2 = F::N2;
+  __shared__ float2 lds[F::LDS_ELEMS];
+  for (int f = blockIdx.x; f < nframes; f += gridDim.x) {
+    float2* x = X + size_t(f) * N * N;
+    float2 v[E];
+    const int t = opaque_tid();
+    if constexpr (!INV) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = x[F::a_y(t, i / N2) * N + F::a_x(t, i / N2, i % N2)];
+      F::forward(v, lds, tw, scale);
+      const int t2 = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) x[F::d_ky(t2, i / N2, i % N2) * N + F::d_kx(t2, i / N2)] = v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = x[F::d_ky(t, i / N2, i % N2) * N + F::d_kx(t, i / N2)];
+      F::inverse(v, lds, tw, scale);
+      const int t2 = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) x[F::a_y(t2, i / N2) * N + F::a_x(t2, i / N2, i % N2)] = v[i];
+    }
+  }
+}
+
+// rows (RB at a time) of large frames
+template <int N, int RB, int T, bool INV>
+__global__ __launch_bounds__(T) void fft_rows_kernel(float2* X, const float2* __restrict__ tw, float scale) {
+  constexpr int LP = N + 1;
+  __shared__ float2 tile[RB * LP];
+  float2* x = X + size_t(blockIdx.y) * N * N + size_t(blockIdx.x) * RB * N;
+  for (int i = threadIdx.x; i < RB * N; i += T) tile[(i / N) * LP + (i % N)] = x[i];
+  __syncthreads();
+  LineTile<N, RB, T>::template run<INV>(tile, LP, 1, tw);
+  __syncthreads();
+  for (int i = threadIdx.x; i < RB * N; i += T) x[i] = cscale(tile[(i / N) * LP + (i % N)], scale);
+}
+
+// columns (CB at a time) of large frames
+template <int N, int CB, int T, bool INV>
+__global__ __launch_bounds__(T) void fft_cols_kernel(float2* X, const float2* __restrict__ tw, float scale) {
+  constexpr int CP = CB + 1;
+  __shared__ float2 tile[N * CP];
+  float2* x = X + size_t(blockIdx.y) * N * N + size_t(blockIdx.x) * CB;
+  for (int i = threadIdx.x; i < N * CB; i += T) tile[(i / CB) * CP + (i % CB)] = x[size_t(i / CB) * N + (i % CB)];
+  __syncthreads();
+  LineTile<N, CB, T>::template run<INV>(tile, 1, CP, tw);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * CB; i += T)
+    x[size_t(i / CB) * N + (i % CB)] = cscale(tile[(i / CB) * CP + (i % CB)], scale);
+}
+
+template <int N, int T>
+static void fft_frames_t(float2* X, int n, const float2* tw, bool inv, hipStream_t st) {
+  const int grid = n < 65535 ? n : 65535;
+  const float sc = 1.f / float(N);
+  if (inv) hipLaunchKernelGGL((fft_frames_kernel<N, T, true>), dim3(grid), dim3(T), 0, st, X, n, tw, sc);
+  else hipLaunchKernelGGL((fft_frames_kernel<N, T, false>), dim3(grid), dim3(T), 0, st, X, n, tw, sc);
+}
+
+template <int N, int RB, int CB, int T>
+static void fft_big_t(float2* X, int n, const float2* tw, bool inv, hipStream_t st) {
+  const float sc = 1.f / float(N);
+  for (int f0 = 0; f0 < n; f0 += 65535) {
+    const int nf = (n - f0) < 65535 ? (n - f0) : 65535;
+    float2* Xs = X + size_t(f0) * N * N;
+    if (inv) {
+      hipLaunchKernelGGL((fft_rows_kernel<N, RB, T, true>), dim3(N / RB, nf), dim3(T), 0, st, Xs, tw, 1.f);
+      hipLaunchKernelGGL((fft_cols_kernel<N, CB, T, true>), dim3(N / CB, nf), dim3(T), 0, st, Xs, tw, sc);
+    } else {
+      hipLaunchKernelGGL((fft_rows_kernel<N, RB, T, false>), dim3(N / RB, nf), dim3(T), 0, st, Xs, tw, 1.f);
+      hipLaunchKernelGGL((fft_cols_kernel<N, CB, T, false>), dim3(N / CB, nf), dim3(T), 0, st, Xs, tw, sc);
+    }
+  }
+}
+
+hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inverse, hipStream_t st) {
+  if (nframes <= 0) return hipSuccess;
+  switch (N) {
+    case 16: fft_frames_t<16, 64>(X, nframes, tw, inverse, st); break;
+    case 32: fft_frames_t<32, 128>(X, nframes, tw, inverse, st); break;
+    case 64: fft_frames_t<64, 512>(X, nframes, tw, inverse, st); break;
+    case 128: fft_frames_t<128, 512>(X, nframes, tw, inverse, st); break;
+    case 256: fft_big_t<256, 32, 32, 256>(X, nframes, tw, inverse, st); break;
+    case 512: fft_big_t<512, 16, 16, 256>(X, nframes, tw, inverse, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- per-step kernels
+// Chunk of C positions starting at k0. Buffers are [..][C][..] with pixels innermost.
+
+// patches of every slice + validity of each position
+__global__ void pl_gather_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int c = blockIdx.y, k = b.k0 + c, NN = b.N * b.N;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, want_pos);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    b.valid[c] = p.ok ? 1 : 0;
+    if (!p.ok) latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
+  }
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  const int y = px / b.N, x = px % b.N;
+  for (int s = 0; s < a.S; ++s) {
+    float2 v = make_float2(0.f, 0.f);
+    if (p.ok) v = bilinear(a.obj + size_t(s) * a.H * a.W, a.W, p, y, x);
+    b.obuf[(size_t(s) * b.C + c) * NN + px] = v;
+  }
+}
+
+// per-position probe modes (OPR weights, or an amplitude per position)
+__global__ void pl_probe_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int cm = blockIdx.y, c = cm / a.M, m = cm % a.M, k = b.k0 + c;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  b.pbuf[size_t(cm) * NN + px] = probe_at(a.probe, a.weights + size_t(k) * a.E, a.E, a.M, NN, m, px);
+}
+
+// X[c][m] = src[c][m] * o_s[c]; src is the per-position probe, the broadcast probe
+// (src_stride 0) or the stored incident wave of slice s
+__global__ void pl_exit_kernel(PlainArgs b, const float2* src, size_t src_stride, const float2* o) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int cm = blockIdx.y, c = cm / a.M, m = cm % a.M;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  const float2 s = src[size_t(c) * src_stride + size_t(m) * NN + px];
+  b.xbuf[size_t(cm) * NN + px] = cmul(s, o[size_t(c) * NN + px]);
+}
+
+__global__ void pl_copy_kernel(float2* dst, const float2* src, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
+// X[f][px] *= tf[px] (or conj(tf))
+__global__ void pl_tf_kernel(float2* X, const float2* __restrict__ tf, int NN, int conj) {
+  const int f = blockIdx.y, px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  const float2 h = tf[px];
+  float2& x = X[size_t(f) * NN + px];
+  x = conj ? cmulc(h, x) : cmul(h, x);
+}
+
+// incoherent sum, loss, dl/dI (one block of 256 threads per position)
+template <int LOSS>
+__global__ __launch_bounds__(256) void pl_loss_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  __shared__ double red[256 / WAVE];
+  const int c = blockIdx.x, k = b.k0 + c, N = b.N, NN = N * N;
+  double lsum = 0.0;
+  const bool ok = b.valid[c] != 0;
+  for (int px = threadIdx.x; px < NN; px += 256) {
+    float I = 0.f;
+    for (int m = 0; m < a.M; ++m) I += cabs2(b.xbuf[(size_t(c) * a.M + m) * NN + px]);
+    const int ci = centred_index(px / N, px % N, N);
+    float l = 0.f, cf = 0.f;
+    if (ok) loss_terms<LOSS>(I, a.imeas[size_t(k) * NN + ci], a.eps, l, cf);
+    if (a.ipred) a.ipred[size_t(k) * NN + ci] = ok ? I : 0.f;
+    b.cbuf[size_t(c) * NN + px] = cf;
+    lsum += double(l);
+  }
+  const double tot = block_sum<256>(lsum, red);
+  if (threadIdx.x == 0) {
+    const bool fin = isfinite(tot);
+    a.loss_part[k] = (ok && fin) ? tot * double(a.lscale) : 0.0;
+    if (!fin) {
+      latch(a.flags, FLAG_NONFINITE);
+      b.valid[c] = 0;
+    }
+  }
+}
+
+// X[c][m] = valid ? gscale * dl/dI * X : 0
+__global__ void pl_residual_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int cm = blockIdx.y, c = cm / a.M;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  float2& x = b.xbuf[size_t(cm) * NN + px];
+  x = b.valid[c] ? cscale(x, a.gscale * b.cbuf[size_t(c) * NN + px]) : make_float2(0.f, 0.f);
+}
+
+// apply_AH: X = Y (invalid positions give zero)
+__global__ void pl_loady_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int cm = blockIdx.y, c = cm / a.M;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  b.xbuf[size_t(cm) * NN + px] =
+      b.valid[c] ? a.Y[(size_t(b.k0) * a.M + cm) * NN + px] : make_float2(0.f, 0.f);
+}
+
+// apply_A: write the far field of valid positions
+__global__ void pl_store_psi_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int cm = blockIdx.y, c = cm / a.M;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  a.psi_out[(size_t(b.k0) * a.M + cm) * NN + px] = b.valid[c] ? b.xbuf[size_t(cm) * NN + px] : make_float2(0.f, 0.f);
+}
+
+// g_patch_s[c] = sum_m conj(src[c][m]) X[c][m];  X[c][m] = conj(o_s[c]) X[c][m]
+__global__ void pl_conj_kernel(PlainArgs b, const float2* src, size_t src_stride, const float2* o, float2* gpatch) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int c = blockIdx.y;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  const float2 oc = o[size_t(c) * NN + px];
+  float2 g = make_float2(0.f, 0.f);
+  for (int m = 0; m < a.M; ++m) {
+    float2& x = b.xbuf[(size_t(c) * a.M + m) * NN + px];
+    g = cadd(g, cmulc(src[size_t(c) * src_stride + size_t(m) * NN + px], x));
+    x = cmulc(oc, x);
+  }
+  gpatch[size_t(c) * NN + px] = g;
+}
+
+// gU[e][m][px] += sum_c w[c][e] gP[c][m][px]  (one thread per (e, m, px); chunks run in order)
+__global__ void pl_probe_grad_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int em = blockIdx.y, e = em / a.M, m = em % a.M;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int c = 0; c < b.C; ++c) {
+    if (!b.valid[c]) continue;
+    const float w = a.weights ? a.weights[size_t(b.k0 + c) * a.E + e] : 1.f;
+    const float2 g = b.xbuf[(size_t(c) * a.M + m) * NN + px];
+    acc.x = fmaf(w, g.x, acc.x);
+    acc.y = fmaf(w, g.y, acc.y);
+  }
+  float2& out = a.gprobe[size_t(em) * NN + px];
+  out = cadd(out, acc);
+}
+
+// g_w[k][e] = sum_m sum_px Re(conj(gP) U[e][m])  (one block per (c, e))
+__global__ __launch_bounds__(256) void pl_weight_grad_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  __shared__ double red[256 / WAVE];
+  const int NN = b.N * b.N;
+  const int c = blockIdx.x, e = blockIdx.y, k = b.k0 + c;
+  double s = 0.0;
+  if (b.valid[c]) {
+    for (int m = 0; m < a.M; ++m)
+      for (int px = threadIdx.x; px < NN; px += 256)
+        s += double(cdotre(b.xbuf[(size_t(c) * a.M + m) * NN + px], a.probe[(size_t(e) * a.M + m) * NN + px]));
+  }
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) a.w_part[size_t(k) * a.E + e] = s;
+}
+
+// naive bilinear scatter: four global atomics per patch pixel
+__global__ void pl_scatter_kernel(PlainArgs b, int s) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int c = blockIdx.y, k = b.k0 + c;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN || !b.valid[c]) return;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, want_pos);
+  const float2 g = b.gbuf[(size_t(s) * b.C + c) * NN + px];
+  const int y = px / b.N, x = px % b.N;
+  float2* base = a.gobj + size_t(s) * a.H * a.W + size_t(p.y0 + y) * a.W + (p.x0 + x);
+  atomic_add_c(base, cscale(g, (1.f - p.fy) * (1.f - p.fx)));
+  if (p.fx > 0.f) atomic_add_c(base + 1, cscale(g, (1.f - p.fy) * p.fx));
+  if (p.fy > 0.f) {
+    atomic_add_c(base + a.W, cscale(g, p.fy * (1.f - p.fx)));
+    if (p.fx > 0.f) atomic_add_c(base + a.W + 1, cscale(g, p.fy * p.fx));
+  }
+}
+
+// position gradient: sum_s sum_px Re(conj(g_o) d o / d(y, x))  (one block per position)
+__global__ __launch_bounds__(256) void pl_posgrad_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  __shared__ double red[2 * (256 / WAVE)];
+  const int NN = b.N * b.N;
+  const int c = blockIdx.x, k = b.k0 + c;
+  double v[2] = {0.0, 0.0};
+  if (b.valid[c]) {
+    const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, true);
+    for (int s = 0; s < a.S; ++s) {
+      const float2* O = a.obj + size_t(s) * a.H * a.W;
+      for (int px = threadIdx.x; px < NN; px += 256) {
+        const int y = px / b.N, x = px % b.N;
+        const float2* r0 = O + size_t(p.y0 + y) * a.W + (p.x0 + x);
+        const float2 A00 = r0[0], A01 = r0[1], A10 = r0[a.W], A11 = r0[a.W + 1];
+        float2 dy, dx;
+        dy.x = (1.f - p.fx) * (A10.x - A00.x) + p.fx * (A11.x - A01.x);
+        dy.y = (1.f - p.fx) * (A10.y - A00.y) + p.fx * (A11.y - A01.y);
+        dx.x = (1.f - p.fy) * (A01.x - A00.x) + p.fy * (A11.x - A10.x);
+        dx.y = (1.f - p.fy) * (A01.y - A00.y) + p.fy * (A11.y - A10.y);
+        const float2 g = b.gbuf[(size_t(s) * b.C + c) * NN + px];
+        v[0] += double(cdotre(g, dy));
+        v[1] += double(cdotre(g, dx));
+      }
+    }
+  }
+  block_sum_n<256, 2>(v, red);
+  if (threadIdx.x == 0) {
+    a.pos_part[2 * k] = v[0];
+    a.pos_part[2 * k + 1] = v[1];
+  }
+}
+
+// ----------------------------------------------------------------------------- driver
+static inline dim3 pix_grid(int NN, int rows) { return dim3(unsigned((NN + 255) / 256), unsigned(rows)); }
+
+hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
+  const CallArgs& a = b.a;
+  const int N = b.N, NN = N * N, C = b.C, M = a.M, S = a.S;
+  const size_t fr = size_t(NN);
+  const bool fwd = a.mode != MODE_APPLY_AH;
+  const dim3 blk(256);
+  hipError_t err;
+
+  hipLaunchKernelGGL(pl_gather_kernel, pix_grid(NN, C), blk, 0, st, b);
+  // incident probe of every position: per-position copy when weighted, else broadcast
+  const float2* P0 = a.probe;
+  size_t P0_stride = 0;
+  if (a.weights) {
+    hipLaunchKernelGGL(pl_probe_kernel, pix_grid(NN, C * M), blk, 0, st, b);
+    P0 = b.pbuf;
+    P0_stride = size_t(M) * fr;
+  }
+  // multislice incident waves: psibuf[s] = [C][M][NN], psibuf[0] = P0
+  auto psi_src = [&](int s, const float2*& src, size_t& stride) {
+    if (s == 0) {
+      src = P0;
+      stride = P0_stride;
+    } else {
+      src = b.psibuf + size_t(s) * C * M * fr;
+      stride = size_t(M) * fr;
+    }
+  };
+
+  if (fwd) {
+    for (int s = 0; s < S; ++s) {
+      const float2* src;
+      size_t stride;
+      psi_src(s, src, stride);
+      hipLaunchKernelGGL(pl_exit_kernel, pix_grid(NN, C * M), blk, 0, st, b, src, stride,
+                         (const float2*)(b.obuf + size_t(s) * C * fr));
+      if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, false, st)) != hipSuccess) return err;
+      if (s < S - 1) {
+        hipLaunchKernelGGL(pl_tf_kernel, pix_grid(NN, C * M), blk, 0, st, b.xbuf, a.tf, NN, 0);
+        if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, true, st)) != hipSuccess) return err;
+        float2* dst = b.psibuf + size_t(s + 1) * C * M * fr;
+        hipLaunchKernelGGL(pl_copy_kernel, dim3(4096), blk, 0, st, dst, (const float2*)b.xbuf, size_t(C) * M * fr);
+      }
+    }
+    if (a.mode == MODE_APPLY_A) {
+      hipLaunchKernelGGL(pl_store_psi_kernel, pix_grid(NN, C * M), blk, 0, st, b);
+      return hipGetLastError();
+    }
+    if (a.loss == 0) hipLaunchKernelGGL(pl_loss_kernel<0>, dim3(C), blk, 0, st, b);
+    else hipLaunchKernelGGL(pl_loss_kernel<1>, dim3(C), blk, 0, st, b);
+    if (a.mode == MODE_FORWARD) return hipGetLastError();
+    hipLaunchKernelGGL(pl_residual_kernel, pix_grid(NN, C * M), blk, 0, st, b);
+  } else {
+    if (S > 1) return hipErrorNotSupported;  // multislice apply_AH needs the fused path
+    hipLaunchKernelGGL(pl_loady_kernel, pix_grid(NN, C * M), blk, 0, st, b);
+  }
+  if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, true, st)) != hipSuccess) return err;
+  for (int s = S - 1; s >= 0; --s) {
+    const float2* src;
+    size_t stride;
+    psi_src(s, src, stride);
+    hipLaunchKernelGGL(pl_conj_kernel, pix_grid(NN, C), blk, 0, st, b, src, stride,
+                       (const float2*)(b.obuf + size_t(s) * C * fr), b.gbuf + size_t(s) * C * fr);
+    if (s > 0) {
+      if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, false, st)) != hipSuccess) return err;
+      hipLaunchKernelGGL(pl_tf_kernel, pix_grid(NN, C * M), blk, 0, st, b.xbuf, a.tf, NN, 1);
+      if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, true, st)) != hipSuccess) return err;
+    }
+  }
+  if ((a.want & WANT_PROBE) && a.gprobe)
+    hipLaunchKernelGGL(pl_probe_grad_kernel, pix_grid(NN, a.E * M), blk, 0, st, b);
+  if ((a.want & WANT_WEIGHTS) && a.weights && a.w_part)
+    hipLaunchKernelGGL(pl_weight_grad_kernel, dim3(C, a.E), blk, 0, st, b);
+  if ((a.want & WANT_OBJ) && a.gobj)
+    for (int s = 0; s < S; ++s) hipLaunchKernelGGL(pl_scatter_kernel, pix_grid(NN, C), blk, 0, st, b, s);
+  if ((a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && a.pos_part)
+    hipLaunchKernelGGL(pl_posgrad_kernel, dim3(C), blk, 0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace ptyhip

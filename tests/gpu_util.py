@@ -1,0 +1,107 @@
+"""Shared helpers of the GPU tests: seeded cases, oracle runs, and the comparison
+protocol (relative L2 over re/im pairs; forward <= 1e-5, gradients <= 1e-4)."""
+from __future__ import annotations
+
+import os
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from synth import workloads as W  # noqa: E402
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def torch_cuda():
+    try:
+        import torch
+    except Exception:  # pragma: no cover
+        pytest.skip("torch missing")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(a):
+    torch = torch_cuda()
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel_l2(got, ref) -> float:
+    g = np.asarray(got, dtype=np.complex128).ravel()
+    r = np.asarray(ref, dtype=np.complex128).ravel()
+    return float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+
+
+def measured(truth, seed: int):
+    """Noisy measured intensities of a truth problem (clean intensities from the oracle)."""
+    _, I_clean = oracle.forward(truth.obj, truth.probe, truth.positions, np.zeros((truth.K, truth.N, truth.N)),
+                                weights=truth.weights, lambda_z=truth.lambda_z)
+    return W.poisson_counts(I_clean, seed)
+
+
+def case(config: int, seed: int = 5, **kw):
+    truth = W.make_config(config, **kw)
+    start = W.perturb(truth, seed)
+    return start, measured(truth, seed + 1)
+
+
+def run_oracle(prob, I_meas, grads, norm_count=None):
+    return oracle.forward_adjoint(prob.obj, prob.probe, prob.positions, I_meas, weights=prob.weights,
+                                  loss=prob.loss, eps=prob.eps, lambda_z=prob.lambda_z, norm_count=norm_count,
+                                  grads=grads)
+
+
+def run_gpu(plan, prob, I_meas, grads, plain=False, want_ipred=True):
+    torch = torch_cuda()
+    w = None if prob.weights is None else dev(prob.weights)
+    ipred = torch.zeros((prob.K, prob.N, prob.N), dtype=torch.float32, device="cuda") if want_ipred else None
+    out = plan.forward_adjoint(dev(prob.obj), dev(prob.probe), dev(prob.positions), dev(I_meas), weights=w,
+                               grads=grads, plain=plain, I_pred=ipred)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["loss"] = float(res["loss"][0])
+    res["flags"] = plan.get_error()
+    return res
+
+
+def compare(got, ref, grads, tag=""):
+    errs = {"loss": abs(got["loss"] - ref["loss"]) / max(abs(ref["loss"]), 1e-300)}
+    if "I_pred" in got:
+        errs["I_pred"] = rel_l2(got["I_pred"], ref["I_pred"])
+    names = {"obj": "g_obj", "probe": "g_probe", "pos": "g_pos", "weights": "g_weights"}
+    for g in grads:
+        errs[names[g]] = rel_l2(got[names[g]], ref[names[g]])
+    print(f"{tag} rel errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        tol = FWD_TOL if k in ("loss", "I_pred") else GRAD_TOL
+        assert v <= tol, f"{tag}: {k} rel err {v:.3e} > {tol}"
+    return errs
+
+
+def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=None):
+    """Small generic problem (random smooth object, random smooth probes, random
+    sub-pixel positions) for shapes no config covers."""
+    rng = np.random.default_rng(seed)
+    obj = np.stack([W.random_object(rng, H, H) for _ in range(S)])
+    probe = np.stack([[W.disk_probe(N, N / 4.0) * np.exp(1j * rng.uniform(0, 1)) * (0.6 ** m)
+                       * (1.0 + 0.3 * W.smooth_field((N, N), 2.0, rng)) for m in range(M)] for _ in range(E)])
+    probe = probe * np.sqrt(1e4 / np.sum(np.abs(probe[0]) ** 2))
+    pos = rng.uniform(0.0, H - N - 1.01, size=(K, 2))
+    w = None
+    if weights == "opr" or (weights is None and E > 1):
+        w = np.concatenate([rng.normal(1.0, 0.1, (K, 1)), rng.normal(0.0, 0.05, (K, E - 1))], axis=1)[:, :E]
+    elif weights == "amp":
+        w = rng.uniform(0.85, 1.15, size=(K, E))
+    truth = W.Problem("custom", obj.astype(np.complex64), probe.astype(np.complex64), pos.astype(np.float32),
+                      None if w is None else w.astype(np.float32), loss, lambda_z=lz)
+    start = W.perturb(truth, seed + 1)
+    return start, measured(truth, seed + 2)

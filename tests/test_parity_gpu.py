@@ -1,0 +1,66 @@
+"""GPU forward/adjoint vs the FP64 oracle on identical seeded inputs, through the C ABI.
+
+Sizes are chosen so that the oracle finishes in seconds while the launches still span
+several persistent rounds (K > number of workgroups) with a ragged tail."""
+import numpy as np
+import pytest
+
+from gpu_util import case, compare, custom_problem, run_gpu, run_oracle, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _needs_gpu():
+    torch_cuda()
+
+
+def _plan(prob, **kw):
+    torch_cuda()
+    from paper_2510_20929_amd import Plan
+    return Plan.for_problem(prob, **kw)
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_config0_full(plain):
+    """Config 0 at its full size: 256^2 object, 64^2 probe, 625 integer raster positions."""
+    start, I = case(0)
+    grads = ("obj", "probe")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"c0 {'plain' if plain else 'fused'}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_config1_reduced(plain):
+    """Config 1 structure (128^2, 4 Hermite-Gauss modes, Poisson, sub-pixel spiral,
+    object/probe/position gradients) on a 400^2 object with 300 positions."""
+    start, I = case(1, H=400, K=300)
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"c1 {'plain' if plain else 'fused'}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("N,M,E", [(16, 1, 1), (32, 2, 3), (64, 3, 2), (128, 1, 4)])
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_opr_and_modes(N, M, E, plain):
+    """Eigenprobes with per-position weights, several modes, every gradient."""
+    start, I = custom_problem(100 + N + M + E, N, M, E, 1, N * 3, 70, loss="poisson" if M > 1 else "amplitude",
+                              weights="opr")
+    grads = ("obj", "probe", "pos", "weights")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"opr N={N} M={M} E={E} {'plain' if plain else 'fused'}")
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_amplitude_weights_single_eigenprobe(plain):
+    """Per-position probe amplitude (E = 1 with weights), as in the batched workload."""
+    start, I = custom_problem(7, 64, 2, 1, 1, 200, 90, weights="amp")
+    grads = ("obj", "probe", "pos", "weights")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"amp-weights {'plain' if plain else 'fused'}")
