@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the ptychographic forward + adjoint on one MI355X.
+
+Workload (config 1 of the synthetic suite): a 1024 x 1024 complex object, four
+orthogonal Hermite-Gauss probe modes of 128 x 128, 2000 positions on a Fermat spiral
+with sub-pixel offsets, Poisson loss, gradients of the object, the probe and the
+positions. One step = one forward + adjoint pass over all 2000 patterns with inputs
+resident in HBM. The fused kernel is timed; the per-step form is timed beside it.
+
+Prints one JSON line. `value` is patterns/s of the fused form.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published)
+
+KERNEL_SOURCES = [
+    "paper_2510_20929_amd/csrc/kernels/fused_small.hip",
+    "paper_2510_20929_amd/csrc/device/fft.hpp",
+    "paper_2510_20929_amd/csrc/device/model.hpp",
+    "paper_2510_20929_amd/csrc/device/common.hpp",
+]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def fft_flops(N: int) -> float:
+    """Conventional flop count of one N x N complex FFT: 5 N^2 log2(N^2)."""
+    return 5.0 * N * N * math.log2(N * N)
+
+
+def algorithmic(prob):
+    """Per-pattern algorithmic FFT flops and HBM bytes of one forward + adjoint pass:
+    2 FFTs per mode (and 2 per propagation and slice); bytes = measured pattern (4 N^2)
+    + position in/out (16) + one read and one write of object and probe amortised."""
+    N, M, S, K = prob.N, prob.M, prob.S, prob.K
+    ffts = M * (2 + 4 * (S - 1))
+    flops = ffts * fft_flops(N)
+    obj_bytes = 2 * prob.S * prob.H * prob.W * 8
+    probe_bytes = 2 * prob.E * M * N * N * 8
+    byts = 4 * N * N + 16 + (obj_bytes + probe_bytes) / K
+    return flops, byts
+
+
+def read_traffic(khash: str):
+    """HBM bytes per launch of the fused kernel from the committed PMC summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "fused_c1_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != khash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(truth, start, budget_s: float = 12.0, max_positions: int = 1500):
+    """The FP64 oracle (as it stands) on the first positions of the same workload,
+    single-threaded on the host. Its own measured intensities come from the oracle."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from synth import workloads as W
+
+    n = min(max_positions, truth.K)
+    sub_t = truth.subset(np.arange(n))
+    sub = start.subset(np.arange(n))
+    with threadpool_limits(limits=1):
+        _, I_clean = oracle.forward(sub_t.obj, sub_t.probe, sub_t.positions, np.zeros((n, truth.N, truth.N)),
+                                    loss=truth.loss)
+        I_meas = W.poisson_counts(I_clean, 4242)
+        done, chunk = 0, 25
+        t0 = time.perf_counter()
+        while done < n and time.perf_counter() - t0 < budget_s:
+            k1 = min(done + chunk, n)
+            oracle.forward_adjoint(sub.obj, sub.probe, sub.positions[done:k1], I_meas[done:k1], loss=sub.loss,
+                                   eps=sub.eps, norm_count=truth.K, grads=("obj", "probe", "pos"))
+            done = k1
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {truth.K} positions of the same workload (FP64 NumPy oracle, "
+                      f"{dt:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-step form")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a 1 GiB device copy (counter calibration for the PMC runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the data-parallel sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2510_20929_amd import Plan
+    from synth import workloads as W
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
+
+    truth = W.make_config(1)
+    start = W.perturb(truth, 21)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    obj, probe, pos = t(start.obj), t(start.probe), t(start.positions)
+    plan = Plan.for_problem(start)
+    # measured intensities: the clean far field of the truth (computed by the library) plus Poisson noise
+    I_clean = torch.empty((truth.K, truth.N, truth.N), dtype=torch.float32, device=dev)
+    plan.forward(t(truth.obj), t(truth.probe), t(truth.positions), torch.zeros_like(I_clean), I_pred=I_clean)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20931)
+    I_meas = torch.poisson(I_clean, generator=gen).contiguous()
+    grads = ("obj", "probe", "pos")
+    out = plan.forward_adjoint(obj, probe, pos, I_meas, grads=grads)
+
+    def step(plain=False):
+        plan.forward_adjoint(obj, probe, pos, I_meas, grads=grads, out=out, plain=plain)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.kernel_time()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = plan.kernel_time()
+    plan.set_timing(False)
+    flags = plan.get_error()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    K = truth.K
+    value = K / (ms_step * 1e-3)
+    k_avg_ms = k_ms / max(k_n, 1)
+
+    flops_pp, bytes_pp = algorithmic(start)
+    achieved_tflops = flops_pp * K / (k_avg_ms * 1e-3) / 1e12
+    hbm_alg_gbs = bytes_pp * K / (k_avg_ms * 1e-3) / 1e9
+    khash = kernel_hash()
+    traffic = read_traffic(khash)
+
+    plain = None
+    if not args.no_plain:
+        step(plain=True)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        plan.kernel_time()
+        tp0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(plain=True)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        p_ms, p_n = plan.kernel_time()
+        plan.set_timing(False)
+        p_step = (tp1 - tp0) * 1e3 / args.plain_steps
+        plain = {"value": K / (p_step * 1e-3), "ms_per_step": p_step, "steps": args.plain_steps,
+                 "kernel_chain_ms": p_ms / max(p_n, 1),
+                 "hbm_alg_frac": bytes_pp * K / (p_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(truth, start)
+
+    line = {
+        "metric": "diffraction patterns/s forward+adjoint at 128² frames (fused vs plain), % HBM peak",
+        "value": value,
+        "unit": "patterns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config 1: 1024x1024 complex object, 4 Hermite-Gauss probe modes of 128x128, "
+                               "2000 Fermat-spiral positions with sub-pixel offsets, Poisson loss, gradients "
+                               "of object, probe and positions",
+                   "frame": 128, "modes": 4, "positions": K, "object": [1024, 1024], "loss": "poisson",
+                   "form": "fused persistent kernel"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": "fused_small_kernel<128,512,1>",
+                     "kernel_ms": k_avg_ms, "flops_per_pattern": flops_pp},
+        "hbm": {"alg_bytes_per_pattern": bytes_pp, "alg_GBs": hbm_alg_gbs, "frac_of_peak": hbm_alg_gbs / HBM_PEAK_GBS},
+        "plain": plain,
+        "fused_vs_plain": (value / plain["value"]) if plain else None,
+        "cpu_baseline": cpu,
+        "error_flags": flags,
+        "kernel_hash": khash,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,9 +95,10 @@ typedef struct {
 typedef struct {
   int32_t variant;      /* fused on-chip kernel thread layout: 0 = 512 threads, 1 = alternative */
   int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
-  int32_t probe_copies; /* probe-gradient partial copies (1..8); 0 = 8 (one per XCD) */
   int32_t recompute;    /* multislice: 1 = recompute incident waves, 0 = store them */
   int32_t plain_chunk;  /* positions per chunk of the per-step path; 0 = auto */
+  int32_t device_atomics; /* fused kernel: 1 = one gradient copy with device-scope atomics;
+                             0 = one partial copy per XCD with L2-resolved atomics, summed after */
 } ptyhip_tune;
 
 typedef struct {
@@ -155,6 +156,14 @@ ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const fl
 ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const float* Y, const float* obj,
                               const float* probe, const float* weights, const float* positions, float* g_obj,
                               float* g_probe);
+
+/* Kernel timing: when enabled, every call records a pair of HIP events on its stream
+ * immediately around its main kernel (the fused kernel, or the whole per-step chain).
+ * ptyhip_plan_kernel_time waits for those events, returns the summed milliseconds and
+ * the number of timed launches since the last read, and resets the tally. Up to 4096
+ * launches are recorded between reads. */
+ptyhip_status ptyhip_plan_set_timing(ptyhip_plan plan, int32_t enable);
+ptyhip_status ptyhip_plan_kernel_time(ptyhip_plan plan, double* total_ms, int32_t* launches);
 
 /* Synchronise `stream` and read the plan's device error latch (PTYHIP_FLAG_*). */
 ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);

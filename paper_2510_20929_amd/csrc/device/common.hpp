@@ -122,6 +122,29 @@ __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   atomic_add_f32(f + 1, v.y);
 }
 
+// The accelerator complex die (XCD) this wave runs on (hardware register XCC_ID).
+// Each XCD has its own L2; an atomic at workgroup scope is resolved in that L2.
+__device__ __forceinline__ int xcc_id() {
+  return int(__builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11))) & 7;
+}
+
+// Float add resolved in the issuing XCD's L2. Only valid on a buffer that no other
+// XCD touches during the kernel (a per-XCD partial copy); the kernel-end release
+// writes the L2 back before the next kernel reads the copies.
+__device__ __forceinline__ void atomic_add_c_l2(float2* p, float2 v) {
+  float* f = reinterpret_cast<float*>(p);
+  __hip_atomic_fetch_add(f, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(f + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Add into the partial copy of this XCD (l2 = true) or into one shared copy with
+// device-scope atomics (l2 = false).
+__device__ __forceinline__ void scatter_add(float2* base, size_t copy_stride, bool l2, int xcc, size_t i,
+                                            float2 v) {
+  if (l2) atomic_add_c_l2(base + size_t(xcc) * copy_stride + i, v);
+  else atomic_add_c(base + i, v);
+}
+
 // ----------------------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -110,6 +110,8 @@ template <> struct Split<512> { static constexpr int N1 = 16, N2 = 32; };
 // the reads of that exchange touch distinct banks within each 16-lane group.
 template <int N, int T>
 struct Frame2D {
+  static_assert(WAVE % Split<N>::N1 == 0 && (T % WAVE == 0 || T == N * Split<N>::N1),
+                "the N1 threads of a row must share a wavefront");
   static constexpr int N1 = Split<N>::N1;
   static constexpr int N2 = Split<N>::N2;
   static constexpr int SLOTS = N * N1;
@@ -130,13 +132,18 @@ struct Frame2D {
   }
   __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ (k2 & (N1 - 1))); }
 
+  // Exchange discipline (3 block barriers per transform): the row stages only touch
+  // rows owned by the wave (the N1 threads of a row are adjacent lanes), and LDS
+  // operations of one wave execute in program order, so their exchanges need only a
+  // compiler fence; the first column stage writes back exactly the cells it read.
+  __device__ __forceinline__ static void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
   // layout A (pixels) -> layout D (frequencies), times `scale`
-  __device__ __forceinline__ static void forward(float2 (&v)[E], float2* lds, const float2* __restrict__ tw_,
+  __device__ __forceinline__ static void forward(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
                                                  float scale) {
     const int t = opaque_tid();
-    const float2* __restrict__ tw = opaque_ptr(tw_);
     __syncthreads();
-    // row stage 1: DFT over n2, twiddle, exchange
+    // row stage 1: DFT over n2, twiddle, exchange within the wave
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, y = s / N1, n1 = s % N1;
@@ -147,7 +154,7 @@ struct Frame2D {
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) lds[y * P + sw(n1, k2)] = u[k2];
     }
-    __syncthreads();
+    wave_fence();
     // row stage 2: DFT over n1 for the thread's k2 values
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -161,7 +168,7 @@ struct Frame2D {
         Dft<N1, false>::run(u);
       }
     }
-    __syncthreads();
+    wave_fence();
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, y = s / N1, q = s % N1;
@@ -171,23 +178,18 @@ struct Frame2D {
         for (int k1 = 0; k1 < N1; ++k1) lds[y * P + q + N1 * jj + N2 * k1] = v[l * N2 + jj * N1 + k1];
     }
     __syncthreads();
-    // column stage 1: thread owns column kx, residue m1; DFT over m2, twiddle
+    // column stage 1 (in place): thread owns column kx, residue m1; DFT over m2, twiddle
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, kx = s % N, m1 = s / N;
-      float2* u = &v[l * N2];
+      float2 u[N2];
 #pragma unroll
       for (int m2 = 0; m2 < N2; ++m2) u[m2] = lds[(m1 + N1 * m2) * P + kx];
       Dft<N2, false>::run(u);
 #pragma unroll
       for (int l2 = 1; l2 < N2; ++l2) u[l2] = cmul(u[l2], tw[m1 * l2]);
-    }
-    __syncthreads();
 #pragma unroll
-    for (int l = 0; l < L; ++l) {
-      const int s = t + T * l, kx = s % N, m1 = s / N;
-#pragma unroll
-      for (int l2 = 0; l2 < N2; ++l2) lds[(m1 + N1 * l2) * P + kx] = v[l * N2 + l2];
+      for (int l2 = 0; l2 < N2; ++l2) lds[(m1 + N1 * l2) * P + kx] = u[l2];
     }
     __syncthreads();
     // column stage 2: DFT over m1
@@ -208,10 +210,9 @@ struct Frame2D {
   }
 
   // layout D (frequencies) -> layout A (pixels): the adjoint of `forward`, times `scale`
-  __device__ __forceinline__ static void inverse(float2 (&v)[E], float2* lds, const float2* __restrict__ tw_,
+  __device__ __forceinline__ static void inverse(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
                                                  float scale) {
     const int t = opaque_tid();
-    const float2* __restrict__ tw = opaque_ptr(tw_);
 #pragma unroll
     for (int l = 0; l < L; ++l)
 #pragma unroll
@@ -228,24 +229,21 @@ struct Frame2D {
       }
     }
     __syncthreads();
+    // column stage 1 adjoint (in place)
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, kx = s % N, m1 = s / N;
-      float2* u = &v[l * N2];
+      float2 u[N2];
 #pragma unroll
       for (int l2 = 0; l2 < N2; ++l2) u[l2] = lds[(m1 + N1 * l2) * P + kx];
 #pragma unroll
       for (int l2 = 1; l2 < N2; ++l2) u[l2] = cmul_conjb(u[l2], tw[m1 * l2]);
       Dft<N2, true>::run(u);
+#pragma unroll
+      for (int m2 = 0; m2 < N2; ++m2) lds[(m1 + N1 * m2) * P + kx] = u[m2];
     }
     __syncthreads();
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-      const int s = t + T * l, kx = s % N, m1 = s / N;
-#pragma unroll
-      for (int m2 = 0; m2 < N2; ++m2) lds[(m1 + N1 * m2) * P + kx] = v[l * N2 + m2];
-    }
-    __syncthreads();
+    // row stage 2 adjoint, exchange within the wave
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, y = s / N1, q = s % N1;
@@ -257,7 +255,7 @@ struct Frame2D {
         Dft<N1, true>::run(u);
       }
     }
-    __syncthreads();
+    wave_fence();
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, y = s / N1, q = s % N1;
@@ -268,7 +266,8 @@ struct Frame2D {
         for (int n1 = 0; n1 < N1; ++n1) lds[y * P + sw(n1, k2)] = v[l * N2 + jj * N1 + n1];
       }
     }
-    __syncthreads();
+    wave_fence();
+    // row stage 1 adjoint
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int s = t + T * l, y = s / N1, n1 = s % N1;

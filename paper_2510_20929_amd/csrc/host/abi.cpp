@@ -47,6 +47,20 @@ static std::vector<float2> fresnel(int N, double lz) {
 
 Plan::~Plan() {
   for (void* p : allocs) (void)hipFree(p);
+  for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+}
+
+constexpr int kTimingPool = 4096;
+
+static void timing_begin(Plan* p, hipStream_t st) {
+  if (p->timing && p->ev_used < int(p->ev_start.size())) (void)hipEventRecord(p->ev_start[p->ev_used], st);
+}
+static void timing_end(Plan* p, hipStream_t st) {
+  if (p->timing && p->ev_used < int(p->ev_start.size())) {
+    (void)hipEventRecord(p->ev_stop[p->ev_used], st);
+    ++p->ev_used;
+  }
 }
 
 template <typename T>
@@ -90,9 +104,13 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
-  p->copies = p->tune.probe_copies > 0 ? std::min(p->tune.probe_copies, 8) : 8;
+  p->l2 = p->tune.device_atomics == 0;
+  p->copies = p->l2 ? 8 : 1;
   p->probe_elems = size_t(E) * M * NN;
   if ((st = dalloc(p, &p->gprobe_part, p->probe_elems * p->copies)) != PTYHIP_OK) return st;
+  p->obj_elems = size_t(S) * d.obj_h * d.obj_w;
+  p->obj_copies = 8;
+  if (p->l2 && (st = dalloc(p, &p->gobj_part, p->obj_elems * p->obj_copies)) != PTYHIP_OK) return st;
 
   // fused kernel: on-chip frames up to 128^2, scratch-resident frames above
   p->on_chip = N <= 128;
@@ -149,7 +167,9 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
 }
 
 // Build the kernel argument block of one call.
-static CallArgs make_args(const Plan* p, int K, int mode, uint32_t flags, const float* obj, const float* probe,
+static bool uses_fused(const Plan* p, bool plain) { return !plain && (p->on_chip || p->big_fused_ready); }
+
+static CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj, const float* probe,
                           const float* weights, const float* positions, const float* I_meas, const float* Y,
                           float* Psi, float* I_pred, float* g_obj, bool want_probe, bool want_pos, bool want_w) {
   const ptyhip_desc& d = p->d;
@@ -163,9 +183,12 @@ static CallArgs make_args(const Plan* p, int K, int mode, uint32_t flags, const 
   a.Y = reinterpret_cast<const float2*>(Y);
   a.psi_out = reinterpret_cast<float2*>(Psi);
   a.ipred = I_pred;
-  a.gobj = reinterpret_cast<float2*>(g_obj);
+  const bool l2 = fused && p->l2;
+  a.gobj = g_obj ? (l2 ? p->gobj_part : reinterpret_cast<float2*>(g_obj)) : nullptr;
+  a.gobj_stride = p->obj_elems;
   a.gprobe = want_probe ? p->gprobe_part : nullptr;
   a.gprobe_copies = p->copies;
+  a.l2_atomics = l2 ? 1 : 0;
   a.loss_part = p->loss_part;
   a.pos_part = want_pos ? p->pos_part : nullptr;
   a.w_part = want_w ? p->w_part : nullptr;
@@ -190,7 +213,6 @@ static CallArgs make_args(const Plan* p, int K, int mode, uint32_t flags, const 
            (want_w ? WANT_WEIGHTS : 0) | (I_pred ? WANT_IPRED : 0);
   a.mode = mode;
   a.recompute = p->tune.recompute ? 1 : 0;
-  (void)flags;
   return a;
 }
 
@@ -199,10 +221,13 @@ static ptyhip_status run_core(Plan* p, const CallArgs& a, bool plain, hipStream_
   if (a.K == 0) return PTYHIP_OK;
   const int N = p->d.frame;
   if (!plain && (p->on_chip || p->big_fused_ready)) {
+    timing_begin(p, st);
     hipError_t e = p->on_chip ? launch_fused_small(a, N, p->tune.variant, p->grid, st)
                               : launch_fused_big(a, N, p->grid, st);
+    timing_end(p, st);
     return e == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
   }
+  timing_begin(p, st);
   for (int k0 = 0; k0 < a.K; k0 += p->chunk) {
     PlainArgs b;
     b.a = a;
@@ -220,6 +245,7 @@ static ptyhip_status run_core(Plan* p, const CallArgs& a, bool plain, hipStream_
     if (e == hipErrorNotSupported) return PTYHIP_EUNSUPPORTED;
     if (e != hipSuccess) return PTYHIP_EHIP;
   }
+  timing_end(p, st);
   return PTYHIP_OK;
 }
 
@@ -230,31 +256,45 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   if (p == nullptr) return PTYHIP_EINVAL;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   const ptyhip_desc& d = p->d;
-  if (!obj || !probe || !positions || !I_meas || !loss) return PTYHIP_EINVAL;
-  if (d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  // per-position arrays may be NULL only when there are no positions
+  if (!obj || !probe || !loss || (K > 0 && (!positions || !I_meas))) return PTYHIP_EINVAL;
+  if (d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
   const bool want_obj = !forward_only && (flags & PTYHIP_GRAD_OBJ);
   const bool want_probe = !forward_only && (flags & PTYHIP_GRAD_PROBE);
   const bool want_pos = !forward_only && (flags & PTYHIP_GRAD_POS);
   const bool want_w = !forward_only && (flags & PTYHIP_GRAD_WEIGHTS);
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;
-  if (want_pos && !g_pos) return PTYHIP_EINVAL;
-  if (want_w && (!g_weights || !weights)) return PTYHIP_EINVAL;
+  if (want_pos && K > 0 && !g_pos) return PTYHIP_EINVAL;
+  if (want_w && K > 0 && (!g_weights || !weights)) return PTYHIP_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   const bool acc = (flags & PTYHIP_ACCUMULATE) != 0;
   const bool any_grad = want_obj || want_probe || want_pos || want_w;
   const int mode = (forward_only || !any_grad) ? MODE_FORWARD : MODE_FWD_ADJ;
-  CallArgs a = make_args(p, K, mode, flags, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
+  const bool plain = (flags & PTYHIP_PLAIN) != 0;
+  const bool fused = uses_fused(p, plain);
+  const bool obj_copies = fused && p->l2 && want_obj;
+  CallArgs a = make_args(p, K, mode, fused, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
                          want_obj ? g_obj : nullptr, want_probe, want_pos, want_w);
-  const size_t obj_floats = size_t(d.n_slices) * d.obj_h * d.obj_w * 2;
-  if (want_obj && !acc && launch_fill(g_obj, obj_floats, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+  if (obj_copies) {
+    if (launch_fill(reinterpret_cast<float*>(p->gobj_part), p->obj_elems * p->obj_copies * 2, 0.f, st) != hipSuccess)
+      return PTYHIP_EHIP;
+  } else if (want_obj && !acc && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) {
+    return PTYHIP_EHIP;
+  }
   if (want_probe &&
       launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
     return PTYHIP_EHIP;
-  ptyhip_status s = run_core(p, a, (flags & PTYHIP_PLAIN) != 0, st);
+  ptyhip_status s = run_core(p, a, plain, st);
   if (s != PTYHIP_OK) return s;
   FinalArgs f;
   std::memset(&f, 0, sizeof(f));
+  if (obj_copies) {
+    f.gobj_part = p->gobj_part;
+    f.g_obj = reinterpret_cast<float2*>(g_obj);
+    f.obj_copies = p->obj_copies;
+    f.obj_elems = p->obj_elems;
+  }
   f.loss_part = p->loss_part;
   f.loss = loss;
   f.pos_part = p->pos_part;
@@ -301,8 +341,8 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 || tune->probe_copies < 0 ||
-               tune->plain_chunk < 0 || tune->recompute < 0))
+  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 ||
+               tune->plain_chunk < 0 || tune->recompute < 0 || tune->device_atomics < 0))
     return PTYHIP_EINVAL;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return PTYHIP_ENOMEM;
@@ -364,8 +404,8 @@ ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const fl
   if (p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  CallArgs a = make_args(p, K, MODE_APPLY_A, 0, obj, probe, weights, positions, nullptr, nullptr, Psi, nullptr,
-                         nullptr, false, false, false);
+  CallArgs a = make_args(p, K, MODE_APPLY_A, uses_fused(p, false), obj, probe, weights, positions, nullptr, nullptr,
+                         Psi, nullptr, nullptr, false, false, false);
   return run_core(p, a, false, st);
 }
 
@@ -380,19 +420,31 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const ptyhip_desc& d = p->d;
-  CallArgs a = make_args(p, K, MODE_APPLY_AH, 0, obj, probe, weights, positions, nullptr, Y, nullptr, nullptr,
+  const bool fused = uses_fused(p, false);
+  const bool obj_copies = fused && p->l2 && g_obj;
+  CallArgs a = make_args(p, K, MODE_APPLY_AH, fused, obj, probe, weights, positions, nullptr, Y, nullptr, nullptr,
                          g_obj, g_probe != nullptr, false, false);
-  if (g_obj && launch_fill(g_obj, size_t(d.n_slices) * d.obj_h * d.obj_w * 2, 0.f, st) != hipSuccess)
+  if (obj_copies) {
+    if (launch_fill(reinterpret_cast<float*>(p->gobj_part), p->obj_elems * p->obj_copies * 2, 0.f, st) != hipSuccess)
+      return PTYHIP_EHIP;
+  } else if (g_obj && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) {
     return PTYHIP_EHIP;
+  }
   if (g_probe &&
       launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
     return PTYHIP_EHIP;
   ptyhip_status s = run_core(p, a, false, st);
   if (s != PTYHIP_OK) return s;
-  if (g_probe) {
+  if (g_probe || obj_copies) {
     FinalArgs f;
     std::memset(&f, 0, sizeof(f));
-    f.gprobe_part = p->gprobe_part;
+    if (obj_copies) {
+      f.gobj_part = p->gobj_part;
+      f.g_obj = reinterpret_cast<float2*>(g_obj);
+      f.obj_copies = p->obj_copies;
+      f.obj_elems = p->obj_elems;
+    }
+    f.gprobe_part = g_probe ? p->gprobe_part : nullptr;
     f.g_probe = reinterpret_cast<float2*>(g_probe);
     f.copies = p->copies;
     f.probe_elems = p->probe_elems;
@@ -400,6 +452,40 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
     f.E = d.n_eig;
     if (launch_finalize(f, st) != hipSuccess) return PTYHIP_EHIP;
   }
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_plan_set_timing(ptyhip_plan plan, int32_t enable) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  if (enable && p->ev_start.empty()) {
+    p->ev_start.resize(kTimingPool);
+    p->ev_stop.resize(kTimingPool);
+    for (int i = 0; i < kTimingPool; ++i) {
+      if (hipEventCreate(&p->ev_start[i]) != hipSuccess || hipEventCreate(&p->ev_stop[i]) != hipSuccess)
+        return PTYHIP_EHIP;
+    }
+  }
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_plan_kernel_time(ptyhip_plan plan, double* total_ms, int32_t* launches) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !total_ms || !launches) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  double tot = 0.0;
+  for (int i = 0; i < p->ev_used; ++i) {
+    if (hipEventSynchronize(p->ev_stop[i]) != hipSuccess) return PTYHIP_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]) != hipSuccess) return PTYHIP_EHIP;
+    tot += double(ms);
+  }
+  *total_ms = tot;
+  *launches = p->ev_used;
+  p->ev_used = 0;
   return PTYHIP_OK;
 }
 

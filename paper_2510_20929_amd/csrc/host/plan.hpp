@@ -31,6 +31,10 @@ struct Plan {
   double* w_part = nullptr;
   float2* gprobe_part = nullptr;
   size_t probe_elems = 0;
+  bool l2 = true;            // per-XCD gradient copies with L2-resolved atomics
+  int obj_copies = 8;
+  size_t obj_elems = 0;
+  float2* gobj_part = nullptr;
   float2* scratch = nullptr;
   size_t scratch_stride = 0;
   size_t scratch_bytes = 0;
@@ -44,6 +48,10 @@ struct Plan {
   float* cbuf = nullptr;
   int* valid = nullptr;
   size_t plain_bytes = 0;
+  // kernel timing (events recorded around the main kernel of each call)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
   // bookkeeping
   size_t bytes = 0;
   std::vector<void*> allocs;

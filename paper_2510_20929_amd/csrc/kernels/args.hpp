@@ -27,9 +27,11 @@ struct CallArgs {
   // outputs (device)
   float2* psi_out;        // apply_A output [K][M][N][N] (unshifted)
   float* ipred;           // [K][N][N] DC-centred, or nullptr
-  float2* gobj;           // [S][H][W], accumulated with atomics, or nullptr
-  float2* gprobe;         // [NCOPY][E][M][N][N] workspace partials, or nullptr
-  int gprobe_copies;      // NCOPY (per-XCD copies)
+  float2* gobj;           // object gradient target(s) [copies][S][H][W], or nullptr
+  size_t gobj_stride;     // elements per object-gradient copy (per-XCD copies)
+  float2* gprobe;         // [copies][E][M][N][N] workspace partials, or nullptr
+  int gprobe_copies;      // number of probe-gradient copies
+  int l2_atomics;         // 1: per-XCD copies with L2-resolved atomics; 0: one copy, device scope
   double* loss_part;      // [K] per-position loss (already normalised)
   double* pos_part;       // [K][2]
   double* w_part;         // [K][E]

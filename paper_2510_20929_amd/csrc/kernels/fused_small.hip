@@ -85,8 +85,15 @@ __device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&
   const bool fin = isfinite(tot);
   if (threadIdx.x == 0) {
     a.loss_part[k] = fin ? tot * double(a.lscale) : 0.0;
-    if (!fin) latch(a.flags, FLAG_NONFINITE);
+    if (!fin) {
+      latch(a.flags, FLAG_NONFINITE);
+      if (a.pos_part) {
+        a.pos_part[2 * k] = 0.0;
+        a.pos_part[2 * k + 1] = 0.0;
+      }
+    }
   }
+  if (!fin && a.w_part && int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = 0.0;
   return fin;
 }
 
@@ -99,14 +106,17 @@ __device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m,
   using C = SmallCtx<N, T>;
   const int t = opaque_tid();
   if ((a.want & WANT_PROBE) && a.gprobe) {
-    float2* gp = a.gprobe + size_t(blockIdx.x % a.gprobe_copies) * a.E * a.M * C::NN;
+    const size_t pstride = size_t(a.E) * a.M * C::NN;
+    const bool l2 = a.l2_atomics != 0;
+    const int xcc = xcc_id();
 #pragma unroll
     for (int i = 0; i < C::E; ++i) {
       const int pix = C::a_pix(t, i);
       if (wk == nullptr) {
-        atomic_add_c(gp + size_t(m) * C::NN + pix, gP[i]);
+        scatter_add(a.gprobe, pstride, l2, xcc, size_t(m) * C::NN + pix, gP[i]);
       } else {
-        for (int e = 0; e < a.E; ++e) atomic_add_c(gp + (size_t(e) * a.M + m) * C::NN + pix, cscale(gP[i], wk[e]));
+        for (int e = 0; e < a.E; ++e)
+          scatter_add(a.gprobe, pstride, l2, xcc, (size_t(e) * a.M + m) * C::NN + pix, cscale(gP[i], wk[e]));
       }
     }
   }
@@ -127,6 +137,8 @@ __device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m,
 template <int N, int T>
 __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p, const float2* lds,
                                            const float2* __restrict__ Os, float2* gOs, double& gy, double& gx) {
+  const bool l2 = a.l2_atomics != 0;
+  const int xcc = xcc_id();
   constexpr int P = Frame2D<N, T>::P;
   const int WH = N + p.ey, WW = N + p.ex;
   const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
@@ -146,7 +158,7 @@ __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p,
       float2 g;
       g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
       g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
-      atomic_add_c(gOs + oi, g);
+      scatter_add(gOs, a.gobj_stride, l2, xcc, oi, g);
     }
     if (want_pos) {
       const float2 A = Os[oi];
@@ -180,23 +192,27 @@ __device__ __forceinline__ void finish_position(const CallArgs& a, int k, double
 
 // ----------------------------------------------------------------------------- single slice
 // Registers hold only the working frame v and dl/dI (3 E floats per thread). The patch
-// o and, with several modes, the running patch gradient sum_m conj(P_m) g_m live in
-// the workgroup's scratch frames ([E][T], coalesced, L2 resident); the finished patch
-// gradient goes straight to LDS on the last mode.
+// o, the far fields of all but the last mode, and (with several modes) the running
+// patch gradient sum_m conj(P_m) g_m live in the workgroup's scratch frames ([E][T],
+// coalesced, L2 resident); the finished patch gradient goes straight to LDS.
 template <int N, int T, int LOSS>
 __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   using F = Frame2D<N, T>;
   using C = SmallCtx<N, T>;
   constexpr int E = C::E;
   __shared__ float2 lds[F::LDS_ELEMS];
+  __shared__ float2 tws[N];
   __shared__ double red[2 * (T / WAVE)];
   __shared__ float wsh[MAX_EIG];
   __shared__ double wacc[MAX_EIG];
   const float inv_n = 1.f / float(N);
   const bool fwd = a.mode != MODE_APPLY_AH;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
+  // scratch: patch [NN], patch-gradient accumulator [NN], far fields of modes 0..M-2 [M-1][NN]
   float2* obuf = a.scratch + size_t(blockIdx.x) * a.scratch_stride;
   float2* gacc = obuf + size_t(C::NN);
+  float2* psis = gacc + size_t(C::NN);
 
   for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -231,9 +247,16 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
           for (int i = 0; i < E; ++i)
             v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
         }
-        F::forward(v, lds, a.tw, inv_n);
+        F::forward(v, lds, tws, inv_n);
 #pragma unroll
         for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
+        if (m < a.M - 1 && a.mode != MODE_APPLY_A) {
+          // keep this mode's far field for the adjoint (the last one stays in registers)
+          const int t = opaque_tid();
+          float2* ps = psis + size_t(m) * C::NN;
+#pragma unroll
+          for (int i = 0; i < E; ++i) ps[size_t(i) * T + t] = v[i];
+        }
         if (a.mode == MODE_APPLY_A) {
           const int t = opaque_tid();
           float2* out = a.psi_out + (size_t(k) * a.M + m) * C::NN;
@@ -246,25 +269,26 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
       if (a.mode == MODE_FORWARD) continue;
     }
 
-    for (int m = 0; m < a.M; ++m) {
+    // adjoint, last mode first (its far field is still in registers)
+    for (int mm = 0; mm < a.M; ++mm) {
+      const int m = a.M - 1 - mm;
       if (!fwd) {
         const int t = opaque_tid();
         const float2* y = a.Y + (size_t(k) * a.M + m) * C::NN;
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = y[C::d_freq(t, i)];
       } else {
-        if (a.M > 1) {
+        if (mm > 0) {
           const int t = opaque_tid();
+          const float2* ps = psis + size_t(m) * C::NN;
 #pragma unroll
-          for (int i = 0; i < E; ++i)
-            v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
-          F::forward(v, lds, a.tw, inv_n);
+          for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
         }
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
       }
-      F::inverse(v, lds, a.tw, inv_n);
-      const bool last = m == a.M - 1;
+      F::inverse(v, lds, tws, inv_n);
+      const bool last = mm == a.M - 1;
       __syncthreads();  // every thread is done reading LDS before the patch gradient lands there
       {
         const int t = opaque_tid();
@@ -273,7 +297,7 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
           const int pix = C::a_pix(t, i);
           float2 go = cmulc(probe_at(a.probe, wk, a.E, a.M, C::NN, m, pix), v[i]);
           const size_t si = size_t(i) * T + t;
-          if (m > 0) go = cadd(go, gacc[si]);
+          if (mm > 0) go = cadd(go, gacc[si]);
           if (last) lds[(pix / N) * F::P + (pix % N)] = go;
           else gacc[si] = go;
           v[i] = cmulc(obuf[si], v[i]);
@@ -299,11 +323,13 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   constexpr int E = C::E;
   constexpr size_t FR = size_t(E) * T;  // one frame in scratch
   __shared__ float2 lds[F::LDS_ELEMS];
+  __shared__ float2 tws[N];
   __shared__ double red[2 * (T / WAVE)];
   __shared__ float wsh[MAX_EIG];
   __shared__ double wacc[MAX_EIG];
   const int tid = threadIdx.x;
   const int S = a.S;
+  for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
   const float inv_n = 1.f / float(N);
   const bool fwd = a.mode != MODE_APPLY_AH;
   const bool recompute = a.recompute || !fwd;
@@ -335,9 +361,9 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
       const int t = opaque_tid();
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
-      F::forward(v, lds, a.tw, inv_n);
+      F::forward(v, lds, tws, inv_n);
       apply_tf(v, false);
-      F::inverse(v, lds, a.tw, inv_n);
+      F::inverse(v, lds, tws, inv_n);
     }
   };
 
@@ -386,10 +412,10 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
           }
 #pragma unroll
           for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
-          F::forward(v, lds, a.tw, inv_n);
+          F::forward(v, lds, tws, inv_n);
           if (s < S - 1) {
             apply_tf(v, false);
-            F::inverse(v, lds, a.tw, inv_n);
+            F::inverse(v, lds, tws, inv_n);
           }
         }
 #pragma unroll
@@ -425,11 +451,11 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
         const int t = opaque_tid();
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = cmul(v[i], o[size_t(i) * T + t]);
-        F::forward(v, lds, a.tw, inv_n);
+        F::forward(v, lds, tws, inv_n);
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
       }
-      F::inverse(v, lds, a.tw, inv_n);
+      F::inverse(v, lds, tws, inv_n);
       for (int s = S - 1; s >= 0; --s) {
         float2 ps[E];
         if (!recompute) {
@@ -450,9 +476,9 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
           v[i] = cmulc(o[si], v[i]);
         }
         if (s > 0) {
-          F::forward(v, lds, a.tw, inv_n);
+          F::forward(v, lds, tws, inv_n);
           apply_tf(v, true);
-          F::inverse(v, lds, a.tw, inv_n);
+          F::inverse(v, lds, tws, inv_n);
         }
       }
       probe_gradients<N, T>(a, k, m, wk, v, red, wacc);
@@ -498,7 +524,7 @@ int fused_small_threads(int N, int variant) {
 
 size_t fused_small_scratch_elems(int N, int S, int M, int recompute) {
   const size_t fr = size_t(N) * N;
-  if (S <= 1) return fr * (M > 1 ? 2 : 1);
+  if (S <= 1) return fr * (M > 1 ? size_t(M) + 1 : 1);
   return fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
 }
 

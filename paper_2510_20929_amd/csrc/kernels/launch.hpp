@@ -31,6 +31,10 @@ struct FinalArgs {
   float2* g_probe;          // [E*M*N*N] or nullptr
   int copies;
   size_t probe_elems;
+  const float2* gobj_part;  // [obj_copies][S*H*W] or nullptr
+  float2* g_obj;            // [S*H*W] or nullptr
+  int obj_copies;
+  size_t obj_elems;
   int K, E;
   int accumulate;
 };

@@ -32,7 +32,8 @@ STATUS = {0: "PTYHIP_OK", 1: "PTYHIP_EINVAL", 2: "PTYHIP_ESHAPE", 3: "PTYHIP_EBO
 EXPORTED = [
     "ptyhip_status_str", "ptyhip_version", "ptyhip_desc_validate", "ptyhip_plan_create", "ptyhip_plan_create_ex",
     "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint", "ptyhip_apply_A",
-    "ptyhip_apply_AH", "ptyhip_get_error", "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
+    "ptyhip_apply_AH", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
+    "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
     "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy",
 ]
 
@@ -45,8 +46,8 @@ class Desc(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("grid", ctypes.c_int32), ("probe_copies", ctypes.c_int32),
-                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32), ("device_atomics", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -87,6 +88,8 @@ def _lib():
         L.ptyhip_forward_adjoint.argtypes = [_vp, _vp, _i32, _u32] + [_vp] * 11
         L.ptyhip_apply_A.argtypes = [_vp, _vp, _i32] + [_vp] * 5
         L.ptyhip_apply_AH.argtypes = [_vp, _vp, _i32] + [_vp] * 7
+        L.ptyhip_plan_set_timing.argtypes = [_vp, _i32]
+        L.ptyhip_plan_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
         L.ptyhip_get_error.argtypes = [_vp, _vp, ctypes.POINTER(_u32)]
         L.ptyhip_clear_error.argtypes = [_vp, _vp]
         L.ptyhip_batch_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(_i32), _i32, ctypes.POINTER(Tune),
@@ -158,8 +161,9 @@ class Plan:
         self.max_positions = int(max_positions)
         h = ctypes.c_void_p()
         if tune:
-            tu = Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)), int(tune.get("probe_copies", 0)),
-                      int(tune.get("recompute", 0)), int(tune.get("plain_chunk", 0)))
+            tu = Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)),
+                      int(tune.get("recompute", 0)), int(tune.get("plain_chunk", 0)),
+                      int(tune.get("device_atomics", 0)))
             st = _lib().ptyhip_plan_create_ex(ctypes.byref(self.desc), self.max_positions, ctypes.byref(tu),
                                               ctypes.byref(h))
         else:
@@ -274,6 +278,16 @@ class Plan:
                                     _ptr(positions), _ptr(g_obj), _ptr(g_probe))
         _check(st, "ptyhip_apply_AH")
         return g_obj, g_probe
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib().ptyhip_plan_set_timing(self._h, 1 if enable else 0), "ptyhip_plan_set_timing")
+
+    def kernel_time(self):
+        """(summed milliseconds, launches) of the main kernel since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int32(0)
+        _check(_lib().ptyhip_plan_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)), "ptyhip_plan_kernel_time")
+        return float(ms.value), int(n.value)
 
     def get_error(self, stream=None) -> int:
         f = ctypes.c_uint32(0)

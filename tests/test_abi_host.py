@@ -1,0 +1,53 @@
+"""Host-side checks that need no GPU: the library loads, exports every symbol the
+header declares, and validates descriptions without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptyhip.h")
+
+
+def _lib():
+    from paper_2510_20929_amd import ptyhip
+    if not os.path.exists(ptyhip.LIB_PATH):
+        pytest.skip("library not built")
+    return ptyhip
+
+
+def test_exports_every_declared_symbol():
+    mod = _lib()
+    decl = set(re.findall(r"\b(ptyhip_[a-z_A-Z]+)\s*\(", open(HEADER).read()))
+    decl = {d for d in decl if not d.endswith("_t")}
+    L = ctypes.CDLL(mod.LIB_PATH)
+    missing = [d for d in sorted(decl) if not hasattr(L, d)]
+    assert not missing, missing
+    assert set(mod.EXPORTED) == decl
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(frame=128, n_modes=4, obj_h=1024, obj_w=1024), 0),
+    (dict(frame=100, obj_h=200, obj_w=200), 7),
+    (dict(frame=8, obj_h=200, obj_w=200), 7),
+    (dict(frame=64, n_modes=0, obj_h=200, obj_w=200), 1),
+    (dict(frame=64, n_eig=17, obj_h=200, obj_w=200), 1),
+    (dict(frame=64, n_slices=0, obj_h=200, obj_w=200), 1),
+    (dict(frame=64, obj_h=63, obj_w=200), 2),
+    (dict(frame=64, obj_h=200, obj_w=200, loss=5), 7),
+    (dict(frame=64, obj_h=200, obj_w=200, poisson_eps=float("nan")), 4),
+    (dict(frame=64, obj_h=200, obj_w=200, poisson_eps=-1.0), 4),
+    (dict(frame=256, n_slices=2, obj_h=600, obj_w=600), 7),
+])
+def test_desc_validate(kw, status):
+    mod = _lib()
+    assert mod.ptyhip_desc_validate(mod.make_desc(**kw)) == status
+
+
+def test_status_strings_and_version():
+    mod = _lib()
+    L = mod.lib()
+    assert L.ptyhip_version().startswith(b"ptyhip")
+    for s in range(8):
+        assert len(L.ptyhip_status_str(s)) > 0

@@ -1,0 +1,74 @@
+"""Device-detected errors latch a flag and drop only the offending position; host-
+detectable errors return a status and launch nothing."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_util import compare, custom_problem, dev, run_gpu, run_oracle, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _needs_gpu():
+    torch_cuda()
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+@pytest.mark.parametrize("kind", ["bounds", "nan_position", "nan_data"])
+def test_bad_position_is_dropped_and_latched(kind, plain):
+    from paper_2510_20929_amd import FLAG_BOUNDS, FLAG_NONFINITE, Plan
+    p, I = custom_problem(41, 64, 2, 1, 1, 192, 30)
+    bad = 7
+    pos = p.positions.copy()
+    I = I.copy()
+    if kind == "bounds":
+        pos[bad] = (190.5, 3.0)
+        expect = FLAG_BOUNDS
+    elif kind == "nan_position":
+        pos[bad, 1] = np.nan
+        expect = FLAG_NONFINITE
+    else:
+        I[bad, 3, 4] = np.nan
+        expect = FLAG_NONFINITE
+    from dataclasses import replace
+    q = replace(p, positions=pos)
+    grads = ("obj", "probe", "pos")
+    keep = np.array([k for k in range(p.K) if k != bad])
+    ref = run_oracle(q.subset(keep), I[keep], grads, norm_count=p.K)
+    plan = Plan.for_problem(q)
+    got = run_gpu(plan, q, I, grads, plain=plain, want_ipred=False)
+    assert got["flags"] & expect
+    assert np.all(got["g_pos"][bad] == 0)
+    got["g_pos"] = got["g_pos"][keep]
+    compare(got, ref, grads, tag=f"{kind} {'plain' if plain else 'fused'}")
+    plan.clear_error()
+    assert plan.get_error() == 0
+
+
+def test_host_errors_launch_nothing():
+    torch = torch_cuda()
+    from paper_2510_20929_amd import Plan, PtyhipError, lib
+    p, I = custom_problem(42, 32, 1, 1, 1, 96, 10)
+    plan = Plan.for_problem(p)
+    o, u, r, m = dev(p.obj), dev(p.probe), dev(p.positions), dev(I)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    L = lib()
+    st = L.ptyhip_forward(plan._h, None, 11, ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(u.data_ptr()), None,
+                          ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                          ctypes.c_void_p(loss.data_ptr()), None)
+    assert st == 3  # K > max_positions
+    st = L.ptyhip_forward(plan._h, None, 10, None, ctypes.c_void_p(u.data_ptr()), None,
+                          ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                          ctypes.c_void_p(loss.data_ptr()), None)
+    assert st == 1  # NULL object
+    st = L.ptyhip_forward_adjoint(plan._h, None, 10, 8, ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                  None, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                  ctypes.c_void_p(loss.data_ptr()), None, None, None, None, None)
+    assert st == 1  # weight gradient without weights
+    out = plan.forward_adjoint(o, u, r[:0], m[:0], grads=("obj", "probe"))
+    torch.cuda.synchronize()
+    assert float(out["loss"][0]) == 0.0 and float(out["g_obj"].abs().max()) == 0.0
+    with pytest.raises(PtyhipError):
+        Plan(100, 1, 1, 1, 200, 200)
