@@ -95,15 +95,15 @@ typedef struct {
 typedef struct {
   int32_t variant;      /* fused on-chip kernel thread layout: 0 = 512 threads, 1 = alternative */
   int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
-  int32_t recompute;    /* multislice: 1 = recompute incident waves, 0 = store them */
+  int32_t recompute;    /* 1 = recompute (multislice: incident waves; several modes: far fields)
+                           instead of keeping them in workgroup scratch */
   int32_t plain_chunk;  /* positions per chunk of the per-step path; 0 = auto */
-  int32_t device_atomics; /* fused kernel: 1 = one gradient copy with device-scope atomics;
-                             0 = one partial copy per XCD with L2-resolved atomics, summed after */
 } ptyhip_tune;
 
 typedef struct {
   size_t workspace_bytes;  /* device memory owned by the plan */
   size_t scratch_bytes;    /* of which per-workgroup scratch of the fused kernel */
+  size_t window_bytes;     /* of which per-position window gradients of the fused form */
   size_t plain_bytes;      /* of which per-step path buffers */
   int32_t grid;            /* fused kernel workgroups */
   int32_t threads;         /* fused kernel threads per workgroup */

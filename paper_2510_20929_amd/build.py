@@ -21,6 +21,7 @@ SOURCES = [
     "kernels/fused_small.hip",
     "kernels/fused_big.hip",
     "kernels/finalize.hip",
+    "kernels/gather.hip",
     "kernels/batched.hip",
     "host/abi.cpp",
     "host/batch.cpp",

@@ -104,23 +104,20 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
-  p->l2 = p->tune.device_atomics == 0;
-  p->copies = p->l2 ? 8 : 1;
+  p->copies = 1;
   p->probe_elems = size_t(E) * M * NN;
-  if ((st = dalloc(p, &p->gprobe_part, p->probe_elems * p->copies)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->gprobe_part, p->probe_elems)) != PTYHIP_OK) return st;
   p->obj_elems = size_t(S) * d.obj_h * d.obj_w;
-  p->obj_copies = 8;
-  if (p->l2 && (st = dalloc(p, &p->gobj_part, p->obj_elems * p->obj_copies)) != PTYHIP_OK) return st;
 
   // fused kernel: on-chip frames up to 128^2, scratch-resident frames above
   p->on_chip = N <= 128;
   const int recompute = p->tune.recompute ? 1 : 0;
   if (p->on_chip) {
     p->threads = fused_small_threads(N, p->tune.variant);
-    p->scratch_stride = fused_small_scratch_elems(N, S, M, recompute);
+    p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off);
   } else {
     p->threads = 256;
-    p->scratch_stride = fused_big_scratch_elems(N, S, M);
+    p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
   }
   int grid = p->tune.grid > 0 ? p->tune.grid : p->cus;
   p->grid = grid;
@@ -128,6 +125,13 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
     if ((st = dalloc(p, &p->scratch, p->scratch_stride * size_t(grid))) != PTYHIP_OK) return st;
     p->scratch_bytes = p->scratch_stride * size_t(grid) * sizeof(float2);
   }
+  // per-position window gradients of the fused form, chunked to a bounded footprint
+  const size_t win = size_t(S) * (N + 1) * (N + 1) * sizeof(float2);
+  const size_t win_budget = size_t(2) << 30;
+  p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(maxK, 1)), win_budget / win)));
+  if ((st = dalloc(p, &p->gwin, size_t(p->fchunk) * S * (N + 1) * (N + 1))) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->wvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
+  p->window_bytes = size_t(p->fchunk) * win;
 
   // per-step path buffers, chunked to a bounded footprint
   const size_t per_pos = NN * sizeof(float2) * (size_t(S) * 2 + size_t(M) * 2 + (S > 1 ? size_t(S) * M : 0)) +
@@ -183,12 +187,10 @@ static CallArgs make_args(const Plan* p, int K, int mode, bool fused, const floa
   a.Y = reinterpret_cast<const float2*>(Y);
   a.psi_out = reinterpret_cast<float2*>(Psi);
   a.ipred = I_pred;
-  const bool l2 = fused && p->l2;
-  a.gobj = g_obj ? (l2 ? p->gobj_part : reinterpret_cast<float2*>(g_obj)) : nullptr;
-  a.gobj_stride = p->obj_elems;
-  a.gprobe = want_probe ? p->gprobe_part : nullptr;
-  a.gprobe_copies = p->copies;
-  a.l2_atomics = l2 ? 1 : 0;
+  a.gobj = (g_obj && !fused) ? reinterpret_cast<float2*>(g_obj) : nullptr;
+  a.gprobe = (want_probe && !fused) ? p->gprobe_part : nullptr;
+  a.gwin = (g_obj && fused) ? p->gwin : nullptr;
+  a.wvalid = fused ? p->wvalid : nullptr;
   a.loss_part = p->loss_part;
   a.pos_part = want_pos ? p->pos_part : nullptr;
   a.w_part = want_w ? p->w_part : nullptr;
@@ -197,6 +199,8 @@ static CallArgs make_args(const Plan* p, int K, int mode, bool fused, const floa
   a.tf = p->tf;
   a.scratch = p->scratch;
   a.scratch_stride = p->scratch_stride;
+  a.pacc_off = p->pacc_off;
+  a.zero_acc = 1;
   a.K = K;
   a.H = d.obj_h;
   a.W = d.obj_w;
@@ -216,36 +220,96 @@ static CallArgs make_args(const Plan* p, int K, int mode, bool fused, const floa
   return a;
 }
 
-// Launch the chosen form over K positions (the plain form runs chunk by chunk).
-static ptyhip_status run_core(Plan* p, const CallArgs& a, bool plain, hipStream_t st) {
-  if (a.K == 0) return PTYHIP_OK;
-  const int N = p->d.frame;
-  if (!plain && (p->on_chip || p->big_fused_ready)) {
+// Per-position arrays of a chunk [k0, k0 + n) of a call.
+static CallArgs chunk_args(const CallArgs& a, int k0, int n, int N, int E, int M) {
+  CallArgs c = a;
+  const size_t NN = size_t(N) * N;
+  c.K = n;
+  c.pos = a.pos ? a.pos + size_t(2) * k0 : nullptr;
+  c.weights = a.weights ? a.weights + size_t(E) * k0 : nullptr;
+  c.imeas = a.imeas ? a.imeas + NN * k0 : nullptr;
+  c.ipred = a.ipred ? a.ipred + NN * k0 : nullptr;
+  c.Y = a.Y ? a.Y + NN * M * k0 : nullptr;
+  c.psi_out = a.psi_out ? a.psi_out + NN * M * k0 : nullptr;
+  c.loss_part = a.loss_part + k0;
+  c.pos_part = a.pos_part ? a.pos_part + size_t(2) * k0 : nullptr;
+  c.w_part = a.w_part ? a.w_part + size_t(E) * k0 : nullptr;
+  c.zero_acc = k0 == 0 ? 1 : 0;
+  return c;
+}
+
+// Run one call in the chosen form, leaving per-position partials in the plan and the
+// object (and, for the fused form, probe) gradient in the caller's buffers.
+static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, float* g_obj, float* g_probe,
+                              hipStream_t st) {
+  const ptyhip_desc& d = p->d;
+  const int N = d.frame;
+  const bool fused = uses_fused(p, plain);
+  const bool adjoint = a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH;
+  const bool want_obj = adjoint && g_obj != nullptr;
+  const bool want_probe = adjoint && g_probe != nullptr;
+  if (!fused) {
+    if (want_obj && !acc && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+    if (want_probe &&
+        launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * 2, 0.f, st) != hipSuccess)
+      return PTYHIP_EHIP;
+    if (a.K == 0) return PTYHIP_OK;
     timing_begin(p, st);
-    hipError_t e = p->on_chip ? launch_fused_small(a, N, p->tune.variant, p->grid, st)
-                              : launch_fused_big(a, N, p->grid, st);
+    for (int k0 = 0; k0 < a.K; k0 += p->chunk) {
+      PlainArgs b;
+      b.a = a;
+      b.N = N;
+      b.C = std::min(p->chunk, a.K - k0);
+      b.k0 = k0;
+      b.obuf = p->obuf;
+      b.pbuf = p->pbuf;
+      b.xbuf = p->xbuf;
+      b.psibuf = p->psibuf;
+      b.gbuf = p->gbuf;
+      b.cbuf = p->cbuf;
+      b.valid = p->valid;
+      hipError_t e = run_plain_chunk(b, st);
+      if (e == hipErrorNotSupported) return PTYHIP_EUNSUPPORTED;
+      if (e != hipSuccess) return PTYHIP_EHIP;
+    }
     timing_end(p, st);
-    return e == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
+    return PTYHIP_OK;
   }
-  timing_begin(p, st);
-  for (int k0 = 0; k0 < a.K; k0 += p->chunk) {
-    PlainArgs b;
-    b.a = a;
-    b.N = N;
-    b.C = std::min(p->chunk, a.K - k0);
-    b.k0 = k0;
-    b.obuf = p->obuf;
-    b.pbuf = p->pbuf;
-    b.xbuf = p->xbuf;
-    b.psibuf = p->psibuf;
-    b.gbuf = p->gbuf;
-    b.cbuf = p->cbuf;
-    b.valid = p->valid;
-    hipError_t e = run_plain_chunk(b, st);
-    if (e == hipErrorNotSupported) return PTYHIP_EUNSUPPORTED;
+  if (a.K == 0) {
+    if (want_obj && !acc && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+    if (want_probe && !acc && launch_fill(g_probe, p->probe_elems * 2, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+    return PTYHIP_OK;
+  }
+  for (int k0 = 0; k0 < a.K; k0 += p->fchunk) {
+    const int n = std::min(p->fchunk, a.K - k0);
+    CallArgs c = chunk_args(a, k0, n, N, d.n_eig, d.n_modes);
+    timing_begin(p, st);
+    hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, p->grid, st)
+                              : launch_fused_big(c, N, p->grid, st);
+    timing_end(p, st);
+    if (e != hipSuccess) return PTYHIP_EHIP;
+    if (want_obj) {
+      GatherArgs g;
+      g.gwin = p->gwin;
+      g.wvalid = p->wvalid;
+      g.pos = c.pos;
+      g.gobj = reinterpret_cast<float2*>(g_obj);
+      g.K = n;
+      g.S = d.n_slices;
+      g.N = N;
+      g.H = d.obj_h;
+      g.W = d.obj_w;
+      g.accumulate = (acc || k0 > 0) ? 1 : 0;
+      if (launch_window_gather(g, st) != hipSuccess) return PTYHIP_EHIP;
+    }
+  }
+  if (want_probe) {
+    hipError_t e = p->on_chip
+                       ? launch_probe_reduce_small(a, N, p->tune.variant, p->grid, reinterpret_cast<float2*>(g_probe),
+                                                   acc ? 1 : 0, st)
+                       : launch_probe_reduce_big(a, N, p->grid, reinterpret_cast<float2*>(g_probe), acc ? 1 : 0, st);
     if (e != hipSuccess) return PTYHIP_EHIP;
   }
-  timing_end(p, st);
   return PTYHIP_OK;
 }
 
@@ -273,28 +337,12 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   const int mode = (forward_only || !any_grad) ? MODE_FORWARD : MODE_FWD_ADJ;
   const bool plain = (flags & PTYHIP_PLAIN) != 0;
   const bool fused = uses_fused(p, plain);
-  const bool obj_copies = fused && p->l2 && want_obj;
   CallArgs a = make_args(p, K, mode, fused, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
                          want_obj ? g_obj : nullptr, want_probe, want_pos, want_w);
-  if (obj_copies) {
-    if (launch_fill(reinterpret_cast<float*>(p->gobj_part), p->obj_elems * p->obj_copies * 2, 0.f, st) != hipSuccess)
-      return PTYHIP_EHIP;
-  } else if (want_obj && !acc && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) {
-    return PTYHIP_EHIP;
-  }
-  if (want_probe &&
-      launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
-    return PTYHIP_EHIP;
-  ptyhip_status s = run_core(p, a, plain, st);
+  ptyhip_status s = run_call(p, a, plain, acc, want_obj ? g_obj : nullptr, want_probe ? g_probe : nullptr, st);
   if (s != PTYHIP_OK) return s;
   FinalArgs f;
   std::memset(&f, 0, sizeof(f));
-  if (obj_copies) {
-    f.gobj_part = p->gobj_part;
-    f.g_obj = reinterpret_cast<float2*>(g_obj);
-    f.obj_copies = p->obj_copies;
-    f.obj_elems = p->obj_elems;
-  }
   f.loss_part = p->loss_part;
   f.loss = loss;
   f.pos_part = p->pos_part;
@@ -302,8 +350,8 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   f.w_part = p->w_part;
   f.g_w = want_w ? g_weights : nullptr;
   f.gprobe_part = p->gprobe_part;
-  f.g_probe = want_probe ? reinterpret_cast<float2*>(g_probe) : nullptr;
-  f.copies = p->copies;
+  f.g_probe = (want_probe && !fused) ? reinterpret_cast<float2*>(g_probe) : nullptr;
+  f.copies = 1;
   f.probe_elems = p->probe_elems;
   f.K = K;
   f.E = d.n_eig;
@@ -341,8 +389,8 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 ||
-               tune->plain_chunk < 0 || tune->recompute < 0 || tune->device_atomics < 0))
+  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 || tune->plain_chunk < 0 ||
+               tune->recompute < 0))
     return PTYHIP_EINVAL;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return PTYHIP_ENOMEM;
@@ -372,6 +420,7 @@ ptyhip_status ptyhip_plan_get_info(ptyhip_plan plan, ptyhip_plan_info* info) {
   if (!p || !info) return PTYHIP_EINVAL;
   info->workspace_bytes = p->bytes;
   info->scratch_bytes = p->scratch_bytes;
+  info->window_bytes = p->window_bytes;
   info->plain_bytes = p->plain_bytes;
   info->grid = p->grid;
   info->threads = p->threads;
@@ -400,13 +449,14 @@ ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const fl
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
-  if (!obj || !probe || !positions || !Psi) return PTYHIP_EINVAL;
-  if (p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  if (!obj || !probe || (K > 0 && (!positions || !Psi))) return PTYHIP_EINVAL;
+  if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  CallArgs a = make_args(p, K, MODE_APPLY_A, uses_fused(p, false), obj, probe, weights, positions, nullptr, nullptr,
-                         Psi, nullptr, nullptr, false, false, false);
-  return run_core(p, a, false, st);
+  const bool fused = uses_fused(p, false);
+  CallArgs a = make_args(p, K, MODE_APPLY_A, fused, obj, probe, weights, positions, nullptr, nullptr, Psi, nullptr,
+                         nullptr, false, false, false);
+  return run_call(p, a, false, false, nullptr, nullptr, st);
 }
 
 ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const float* Y, const float* obj,
@@ -415,41 +465,24 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
-  if (!Y || !obj || !probe || !positions) return PTYHIP_EINVAL;
-  if (p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  if (!obj || !probe || (K > 0 && (!Y || !positions))) return PTYHIP_EINVAL;
+  if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const ptyhip_desc& d = p->d;
   const bool fused = uses_fused(p, false);
-  const bool obj_copies = fused && p->l2 && g_obj;
   CallArgs a = make_args(p, K, MODE_APPLY_AH, fused, obj, probe, weights, positions, nullptr, Y, nullptr, nullptr,
                          g_obj, g_probe != nullptr, false, false);
-  if (obj_copies) {
-    if (launch_fill(reinterpret_cast<float*>(p->gobj_part), p->obj_elems * p->obj_copies * 2, 0.f, st) != hipSuccess)
-      return PTYHIP_EHIP;
-  } else if (g_obj && launch_fill(g_obj, p->obj_elems * 2, 0.f, st) != hipSuccess) {
-    return PTYHIP_EHIP;
-  }
-  if (g_probe &&
-      launch_fill(reinterpret_cast<float*>(p->gprobe_part), p->probe_elems * p->copies * 2, 0.f, st) != hipSuccess)
-    return PTYHIP_EHIP;
-  ptyhip_status s = run_core(p, a, false, st);
+  ptyhip_status s = run_call(p, a, false, false, g_obj, g_probe, st);
   if (s != PTYHIP_OK) return s;
-  if (g_probe || obj_copies) {
+  if (g_probe && !fused) {
     FinalArgs f;
     std::memset(&f, 0, sizeof(f));
-    if (obj_copies) {
-      f.gobj_part = p->gobj_part;
-      f.g_obj = reinterpret_cast<float2*>(g_obj);
-      f.obj_copies = p->obj_copies;
-      f.obj_elems = p->obj_elems;
-    }
-    f.gprobe_part = g_probe ? p->gprobe_part : nullptr;
+    f.gprobe_part = p->gprobe_part;
     f.g_probe = reinterpret_cast<float2*>(g_probe);
-    f.copies = p->copies;
+    f.copies = 1;
     f.probe_elems = p->probe_elems;
     f.K = K;
-    f.E = d.n_eig;
+    f.E = p->d.n_eig;
     if (launch_finalize(f, st) != hipSuccess) return PTYHIP_EHIP;
   }
   return PTYHIP_OK;

@@ -21,7 +21,7 @@ struct Plan {
   bool big_fused_ready = false;
   int threads = 0;
   int grid = 0;
-  int copies = 8;
+  int copies = 1;
   // tables and per-call partials
   float2* tw = nullptr;
   float2* tf = nullptr;
@@ -31,11 +31,13 @@ struct Plan {
   double* w_part = nullptr;
   float2* gprobe_part = nullptr;
   size_t probe_elems = 0;
-  bool l2 = true;            // per-XCD gradient copies with L2-resolved atomics
-  int obj_copies = 8;
   size_t obj_elems = 0;
-  float2* gobj_part = nullptr;
   float2* scratch = nullptr;
+  size_t pacc_off = 0;       // probe-gradient accumulator inside each workgroup's scratch
+  int fchunk = 0;            // positions per fused launch (bounded window buffer)
+  float2* gwin = nullptr;    // [fchunk][S][N+1][N+1] window gradients
+  int* wvalid = nullptr;     // [fchunk]
+  size_t window_bytes = 0;
   size_t scratch_stride = 0;
   size_t scratch_bytes = 0;
   // per-step form

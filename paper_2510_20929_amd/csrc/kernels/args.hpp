@@ -27,11 +27,10 @@ struct CallArgs {
   // outputs (device)
   float2* psi_out;        // apply_A output [K][M][N][N] (unshifted)
   float* ipred;           // [K][N][N] DC-centred, or nullptr
-  float2* gobj;           // object gradient target(s) [copies][S][H][W], or nullptr
-  size_t gobj_stride;     // elements per object-gradient copy (per-XCD copies)
-  float2* gprobe;         // [copies][E][M][N][N] workspace partials, or nullptr
-  int gprobe_copies;      // number of probe-gradient copies
-  int l2_atomics;         // 1: per-XCD copies with L2-resolved atomics; 0: one copy, device scope
+  float2* gobj;           // per-step form: object gradient [S][H][W] (atomics), or nullptr
+  float2* gprobe;         // per-step form: probe gradient partial [E][M][N][N], or nullptr
+  float2* gwin;           // fused form: window gradients [K][S][N+1][N+1], or nullptr
+  int* wvalid;            // fused form: 1 where a position's window gradient was written
   double* loss_part;      // [K] per-position loss (already normalised)
   double* pos_part;       // [K][2]
   double* w_part;         // [K][E]
@@ -41,6 +40,8 @@ struct CallArgs {
   const float2* tf;       // Fresnel transfer function [N][N] (unshifted), S > 1
   float2* scratch;        // per-workgroup scratch base
   size_t scratch_stride;  // float2 elements per workgroup
+  size_t pacc_off;        // offset of the probe-gradient accumulator in a workgroup's scratch
+  int zero_acc;           // clear the probe-gradient accumulators first
   // sizes
   int K, H, W, M, E, S;
   int loss;               // 0 amplitude, 1 Poisson

@@ -23,13 +23,6 @@ __global__ void finalize_elems_kernel(FinalArgs f) {
   if (f.g_w && f.w_part)
     for (size_t i = tid; i < size_t(f.K) * f.E; i += stride)
       f.g_w[i] = f.accumulate ? f.g_w[i] + float(f.w_part[i]) : float(f.w_part[i]);
-  if (f.g_obj && f.gobj_part) {
-    for (size_t i = tid; i < f.obj_elems; i += stride) {
-      float2 s = f.accumulate ? f.g_obj[i] : make_float2(0.f, 0.f);
-      for (int c = 0; c < f.obj_copies; ++c) s = cadd(s, f.gobj_part[size_t(c) * f.obj_elems + i]);
-      f.g_obj[i] = s;
-    }
-  }
   if (f.g_probe && f.gprobe_part) {
     for (size_t i = tid; i < f.probe_elems; i += stride) {
       float2 s = f.accumulate ? f.g_probe[i] : make_float2(0.f, 0.f);
@@ -45,7 +38,6 @@ hipError_t launch_finalize(const FinalArgs& f, hipStream_t st) {
   if (f.g_pos) n = size_t(f.K) * 2;
   if (f.g_w && size_t(f.K) * f.E > n) n = size_t(f.K) * f.E;
   if (f.g_probe && f.probe_elems > n) n = f.probe_elems;
-  if (f.g_obj && f.gobj_part && f.obj_elems > n) n = f.obj_elems;
   if (n > 0) {
     size_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;

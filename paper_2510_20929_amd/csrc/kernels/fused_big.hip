@@ -5,11 +5,24 @@
 
 namespace ptyhip {
 
-size_t fused_big_scratch_elems(int N, int S, int M) {
+size_t fused_big_scratch_elems(int N, int S, int M, int E, size_t* pacc_off) {
   (void)N;
   (void)S;
   (void)M;
+  (void)E;
+  *pacc_off = 0;
   return 0;
+}
+
+hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g_probe, int accumulate,
+                                   hipStream_t st) {
+  (void)a;
+  (void)N;
+  (void)grid;
+  (void)g_probe;
+  (void)accumulate;
+  (void)st;
+  return hipErrorNotSupported;
 }
 
 hipError_t launch_fused_big(const CallArgs& a, int N, int grid, hipStream_t st) {

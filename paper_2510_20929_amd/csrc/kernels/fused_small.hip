@@ -3,17 +3,21 @@
 // One workgroup owns one scan position at a time (positions are strided over a
 // persistent grid, so the workgroups in flight cover a compact stretch of the scan
 // and share object rows in L2). For each position it
-//   gathers the bilinear object patch (registers),
+//   gathers the bilinear object patch,
 //   forms each mode's exit wave, transforms it (registers + LDS), sums |Psi|^2,
 //   evaluates the loss against the measured pattern and dl/dI,
 //   scales each mode's far field by 2 dl/dI / (K_norm N^2) and transforms back,
 //   forms the patch gradient sum_m conj(P_m) g_m and the probe gradient conj(o) g_m,
 //   and finally builds the (N+1)^2 object-window gradient in LDS from the patch
-//   gradient (the transpose of the bilinear gather), adding it to the object
-//   gradient with one atomic per window pixel, while the same pass reduces the
-//   position gradient.
-// Multislice: incident waves and patches of every slice live in a per-workgroup
-// scratch area (L2/MALL resident), or the incident waves are recomputed.
+//   gradient (the transpose of the bilinear gather) and reduces the position gradient.
+//
+// No atomics: float atomics are the scarce resource on this path. Each workgroup
+// accumulates its probe gradient in its own scratch slice (plain read-modify-write),
+// and each position's window gradient is written to a window buffer; small follow-up
+// kernels sum the slices and gather the windows into the object gradient in a fixed
+// order, so the gradients are bitwise reproducible.
+// Multislice: incident waves and patches of every slice live in the workgroup
+// scratch (L2/MALL resident), or the incident waves are recomputed.
 #include "../device/fft.hpp"
 #include "../device/model.hpp"
 #include "launch.hpp"
@@ -29,6 +33,7 @@ struct SmallCtx {
   static constexpr int L = F::L;
   static constexpr int N2 = F::N2;
   static constexpr int NN = N * N;
+  static constexpr int WN = N + 1;  // window side
   __device__ __forceinline__ static int a_pix(int t, int i) {
     const int l = i / N2, j = i % N2;
     return F::a_y(t, l) * N + F::a_x(t, l, j);
@@ -55,6 +60,7 @@ __device__ __forceinline__ void skip_position(const CallArgs& a, int k, const Po
       a.pos_part[2 * k] = 0.0;
       a.pos_part[2 * k + 1] = 0.0;
     }
+    if (a.wvalid) a.wvalid[k] = 0;
   }
   if (a.w_part && tid < a.E) a.w_part[size_t(k) * a.E + tid] = 0.0;
   if (a.ipred)
@@ -91,32 +97,41 @@ __device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&
         a.pos_part[2 * k] = 0.0;
         a.pos_part[2 * k + 1] = 0.0;
       }
+      if (a.wvalid) a.wvalid[k] = 0;
     }
   }
   if (!fin && a.w_part && int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = 0.0;
   return fin;
 }
 
-// Probe-side gradients of one mode from the gradient g of the incident probe wave
-// (layout A): atomics into the probe partials and the OPR weight-gradient sums.
+// Zero this workgroup's probe-gradient accumulator ([E][M] scratch frames).
 template <int N, int T>
-__device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m, const float* wk,
-                                                const float2 (&gP)[Frame2D<N, T>::E], double* red,
+__device__ __forceinline__ void zero_probe_acc(const CallArgs& a, float2* acc) {
+  const size_t n = size_t(a.E) * a.M * N * N;
+  for (size_t i = threadIdx.x; i < n; i += T) acc[i] = make_float2(0.f, 0.f);
+}
+
+// Probe-side gradients of one mode from the gradient gP of the incident probe wave
+// (layout A): accumulate w_e gP into the workgroup's accumulator frames, and the
+// OPR weight-gradient sums Re<gP, U_e,m>.
+template <int N, int T>
+__device__ __forceinline__ void probe_gradients(const CallArgs& a, int m, const float* wk,
+                                                const float2 (&gP)[Frame2D<N, T>::E], float2* acc, double* red,
                                                 double* wacc) {
   using C = SmallCtx<N, T>;
   const int t = opaque_tid();
-  if ((a.want & WANT_PROBE) && a.gprobe) {
-    const size_t pstride = size_t(a.E) * a.M * C::NN;
-    const bool l2 = a.l2_atomics != 0;
-    const int xcc = xcc_id();
+  if ((a.want & WANT_PROBE) && acc) {
+    const int ne = wk ? a.E : 1;
+    for (int e = 0; e < ne; ++e) {
+      float2* fr = acc + (size_t(e) * a.M + m) * C::NN;
+      const float w = wk ? wk[e] : 1.f;
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) {
-      const int pix = C::a_pix(t, i);
-      if (wk == nullptr) {
-        scatter_add(a.gprobe, pstride, l2, xcc, size_t(m) * C::NN + pix, gP[i]);
-      } else {
-        for (int e = 0; e < a.E; ++e)
-          scatter_add(a.gprobe, pstride, l2, xcc, (size_t(e) * a.M + m) * C::NN + pix, cscale(gP[i], wk[e]));
+      for (int i = 0; i < C::E; ++i) {
+        const size_t si = size_t(i) * T + t;
+        float2 g = fr[si];
+        g.x = fmaf(w, gP[i].x, g.x);
+        g.y = fmaf(w, gP[i].y, g.y);
+        fr[si] = g;
       }
     }
   }
@@ -133,35 +148,33 @@ __device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m,
 }
 
 // Object-window pass for one slice: LDS holds the patch gradient in natural order.
-// Adds the bilinear-transposed window into gobj and accumulates the position gradient.
+// Writes the bilinear-transposed (N+1)^2 window gradient and accumulates the position
+// gradient (which reads the object window; requested only with a full window).
 template <int N, int T>
 __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p, const float2* lds,
-                                           const float2* __restrict__ Os, float2* gOs, double& gy, double& gx) {
-  const bool l2 = a.l2_atomics != 0;
-  const int xcc = xcc_id();
+                                           const float2* __restrict__ Os, float2* gwin, double& gy, double& gx) {
   constexpr int P = Frame2D<N, T>::P;
-  const int WH = N + p.ey, WW = N + p.ex;
+  constexpr int WN = N + 1;
   const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
   const float w10 = p.fy * (1.f - p.fx), w11 = p.fy * p.fx;
-  const bool want_obj = (a.want & WANT_OBJ) && gOs != nullptr;
+  const bool want_obj = (a.want & WANT_OBJ) && gwin != nullptr;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
   const float2 z = make_float2(0.f, 0.f);
-  for (int idx = threadIdx.x; idx < WH * WW; idx += T) {
-    const int py = idx / WW, px = idx - py * WW;
+  for (int idx = threadIdx.x; idx < WN * WN; idx += T) {
+    const int py = idx / WN, px = idx - py * WN;
     const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
     const float2 g00 = (iy0 && ix0) ? lds[py * P + px] : z;
     const float2 g01 = (iy0 && ix1) ? lds[py * P + px - 1] : z;
     const float2 g10 = (iy1 && ix0) ? lds[(py - 1) * P + px] : z;
     const float2 g11 = (iy1 && ix1) ? lds[(py - 1) * P + px - 1] : z;
-    const size_t oi = size_t(p.y0 + py) * a.W + (p.x0 + px);
     if (want_obj) {
       float2 g;
       g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
       g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
-      scatter_add(gOs, a.gobj_stride, l2, xcc, oi, g);
+      gwin[idx] = g;
     }
     if (want_pos) {
-      const float2 A = Os[oi];
+      const float2 A = Os[size_t(p.y0 + py) * a.W + (p.x0 + px)];
       float2 hy, hx;
       hy.x = (1.f - p.fx) * (g10.x - g00.x) + p.fx * (g11.x - g01.x);
       hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
@@ -188,13 +201,14 @@ __device__ __forceinline__ void finish_position(const CallArgs& a, int k, double
     __syncthreads();
     if (int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = wacc[threadIdx.x];
   }
+  if (threadIdx.x == 0 && a.wvalid) a.wvalid[k] = 1;
 }
 
 // ----------------------------------------------------------------------------- single slice
-// Registers hold only the working frame v and dl/dI (3 E floats per thread). The patch
-// o, the far fields of all but the last mode, and (with several modes) the running
-// patch gradient sum_m conj(P_m) g_m live in the workgroup's scratch frames ([E][T],
-// coalesced, L2 resident); the finished patch gradient goes straight to LDS.
+// Registers hold only the working frame v and dl/dI (3 E floats per thread). The
+// workgroup's scratch ([E][T] frames, coalesced) holds the patch o, the running patch
+// gradient sum_m conj(P_m) g_m (several modes), the far fields of all but the last
+// mode (unless they are recomputed), and the probe-gradient accumulator.
 template <int N, int T, int LOSS>
 __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   using F = Frame2D<N, T>;
@@ -207,12 +221,16 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   __shared__ double wacc[MAX_EIG];
   const float inv_n = 1.f / float(N);
   const bool fwd = a.mode != MODE_APPLY_AH;
+  const bool adj = a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
   for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
-  // scratch: patch [NN], patch-gradient accumulator [NN], far fields of modes 0..M-2 [M-1][NN]
+  // scratch: patch [NN], patch-gradient accumulator [NN], far fields of modes 0..M-2,
+  // probe-gradient accumulator [E][M][NN]
   float2* obuf = a.scratch + size_t(blockIdx.x) * a.scratch_stride;
   float2* gacc = obuf + size_t(C::NN);
   float2* psis = gacc + size_t(C::NN);
+  float2* pacc = obuf + a.pacc_off;
+  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
 
   for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -250,7 +268,7 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
         F::forward(v, lds, tws, inv_n);
 #pragma unroll
         for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
-        if (m < a.M - 1 && a.mode != MODE_APPLY_A) {
+        if (m < a.M - 1 && a.mode == MODE_FWD_ADJ && !a.recompute) {
           // keep this mode's far field for the adjoint (the last one stays in registers)
           const int t = opaque_tid();
           float2* ps = psis + size_t(m) * C::NN;
@@ -280,9 +298,17 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
       } else {
         if (mm > 0) {
           const int t = opaque_tid();
-          const float2* ps = psis + size_t(m) * C::NN;
+          if (a.recompute) {
+            // recompute this mode's far field instead of reading it back
 #pragma unroll
-          for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
+            for (int i = 0; i < E; ++i)
+              v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+            F::forward(v, lds, tws, inv_n);
+          } else {
+            const float2* ps = psis + size_t(m) * C::NN;
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
+          }
         }
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
@@ -303,19 +329,20 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
           v[i] = cmulc(obuf[si], v[i]);
         }
       }
-      probe_gradients<N, T>(a, k, m, wk, v, red, wacc);
+      probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);
     }
 
     __syncthreads();
     double gy = 0.0, gx = 0.0;
-    window_pass<N, T>(a, p, lds, a.obj, a.gobj, gy, gx);
+    window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);
     finish_position<N, T>(a, k, gy, gx, red, wacc);
   }
 }
 
 // ----------------------------------------------------------------------------- multislice
-// Scratch per workgroup (float2 elements, element i of thread t at i*T + t):
-//   patches [S][E*T], incident waves [M][S][E*T] (unless recomputed), patch gradients [S][E*T]
+// Scratch per workgroup (element i of thread t at i*T + t):
+//   patches [S][NN], patch gradients [S][NN], incident waves [M][S][NN] (unless
+//   recomputed), probe-gradient accumulator [E][M][NN] at pacc_off.
 template <int N, int T, int LOSS>
 __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   using F = Frame2D<N, T>;
@@ -332,13 +359,16 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
   const float inv_n = 1.f / float(N);
   const bool fwd = a.mode != MODE_APPLY_AH;
+  const bool adj = a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH;
   const bool recompute = a.recompute || !fwd;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
   float2* scr = a.scratch + size_t(blockIdx.x) * a.scratch_stride;
   float2* Op = scr;                                   // [S][FR]
   float2* Gp = Op + size_t(S) * FR;                   // [S][FR]
   float2* Ps = Gp + size_t(S) * FR;                   // [M][S][FR]
+  float2* pacc = scr + a.pacc_off;
   const size_t HW = size_t(a.H) * a.W;
+  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
 
   // multiply by the slice transfer function (or its conjugate) in layout D
   auto apply_tf = [&](float2 (&v)[E], bool conj) {
@@ -481,7 +511,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
           F::inverse(v, lds, tws, inv_n);
         }
       }
-      probe_gradients<N, T>(a, k, m, wk, v, red, wacc);
+      probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);
     }
 
     double gy = 0.0, gx = 0.0;
@@ -492,9 +522,29 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
 #pragma unroll
       for (int i = 0; i < E; ++i) go[i] = g[size_t(i) * T + t];
       F::store_natural(go, lds);
-      window_pass<N, T>(a, p, lds, a.obj + size_t(s) * HW, a.gobj ? a.gobj + size_t(s) * HW : nullptr, gy, gx);
+      window_pass<N, T>(a, p, lds, a.obj + size_t(s) * HW,
+                        a.gwin ? a.gwin + (size_t(k) * S + s) * C::WN * C::WN : nullptr, gy, gx);
     }
     finish_position<N, T>(a, k, gy, gx, red, wacc);
+  }
+}
+
+// ----------------------------------------------------------------------------- probe reduction
+// g_probe[e][m][pix] (+)= sum over workgroups of their accumulator frames, mapping the
+// scratch element i*T + t back to pixel a_pix(t, i).
+template <int N, int T>
+__global__ void probe_reduce_kernel(const float2* __restrict__ scratch, size_t stride, size_t pacc_off, int groups,
+                                    int EM, float2* g_probe, int accumulate) {
+  using C = SmallCtx<N, T>;
+  const size_t n = size_t(EM) * C::NN;
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += size_t(gridDim.x) * blockDim.x) {
+    const size_t em = g / C::NN, r = g % C::NN;
+    const int i = int(r / T), t = int(r % T);
+    const float2* src = scratch + pacc_off + em * C::NN + r;
+    float2 s = make_float2(0.f, 0.f);
+    for (int w = 0; w < groups; ++w) s = cadd(s, src[size_t(w) * stride]);
+    float2* dst = g_probe + em * C::NN + C::a_pix(t, i);
+    *dst = accumulate ? cadd(*dst, s) : s;
   }
 }
 
@@ -512,6 +562,16 @@ static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int N, int T>
+static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, int accumulate, hipStream_t st) {
+  const size_t n = size_t(a.E) * a.M * N * N;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((probe_reduce_kernel<N, T>), dim3(unsigned(blocks)), dim3(256), 0, st, a.scratch,
+                     a.scratch_stride, a.pacc_off, grid, a.E * a.M, g_probe, accumulate);
+  return hipGetLastError();
+}
+
 int fused_small_threads(int N, int variant) {
   switch (N) {
     case 16: return 64;
@@ -522,10 +582,14 @@ int fused_small_threads(int N, int variant) {
   }
 }
 
-size_t fused_small_scratch_elems(int N, int S, int M, int recompute) {
+// per-workgroup scratch (float2 elements) and the offset of the probe accumulator
+size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off) {
   const size_t fr = size_t(N) * N;
-  if (S <= 1) return fr * (M > 1 ? size_t(M) + 1 : 1);
-  return fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  size_t base;
+  if (S <= 1) base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
+  else base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  *pacc_off = base;
+  return base + fr * size_t(E) * M;
 }
 
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st) {
@@ -534,6 +598,21 @@ hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, h
     case 32: return launch_small_t<32, 128>(a, grid, st);
     case 64: return variant == 1 ? launch_small_t<64, 256>(a, grid, st) : launch_small_t<64, 512>(a, grid, st);
     case 128: return variant == 1 ? launch_small_t<128, 1024>(a, grid, st) : launch_small_t<128, 512>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
+                                     int accumulate, hipStream_t st) {
+  switch (N) {
+    case 16: return probe_reduce_t<16, 64>(a, grid, g_probe, accumulate, st);
+    case 32: return probe_reduce_t<32, 128>(a, grid, g_probe, accumulate, st);
+    case 64:
+      return variant == 1 ? probe_reduce_t<64, 256>(a, grid, g_probe, accumulate, st)
+                          : probe_reduce_t<64, 512>(a, grid, g_probe, accumulate, st);
+    case 128:
+      return variant == 1 ? probe_reduce_t<128, 1024>(a, grid, g_probe, accumulate, st)
+                          : probe_reduce_t<128, 512>(a, grid, g_probe, accumulate, st);
     default: return hipErrorInvalidValue;
   }
 }

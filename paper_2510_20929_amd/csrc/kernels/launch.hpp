@@ -31,24 +31,35 @@ struct FinalArgs {
   float2* g_probe;          // [E*M*N*N] or nullptr
   int copies;
   size_t probe_elems;
-  const float2* gobj_part;  // [obj_copies][S*H*W] or nullptr
-  float2* g_obj;            // [S*H*W] or nullptr
-  int obj_copies;
-  size_t obj_elems;
   int K, E;
   int accumulate;
 };
 
+// Gather of the per-position window gradients into the object gradient.
+struct GatherArgs {
+  const float2* gwin;  // [K][S][N+1][N+1]
+  const int* wvalid;   // [K]
+  const float* pos;    // [K][2]
+  float2* gobj;        // [S][H][W]
+  int K, S, N, H, W;
+  int accumulate;
+};
+
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st);
+hipError_t launch_window_gather(const GatherArgs& g, hipStream_t st);
 hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inverse, hipStream_t st);
 hipError_t run_plain_chunk(PlainArgs b, hipStream_t st);
 
 int fused_small_threads(int N, int variant);
-size_t fused_small_scratch_elems(int N, int S, int M, int recompute);
+size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off);
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
+hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
+                                     int accumulate, hipStream_t st);
 
-size_t fused_big_scratch_elems(int N, int S, int M);
+size_t fused_big_scratch_elems(int N, int S, int M, int E, size_t* pacc_off);
 hipError_t launch_fused_big(const CallArgs& a, int N, int grid, hipStream_t st);
+hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g_probe, int accumulate,
+                                   hipStream_t st);
 
 hipError_t launch_finalize(const FinalArgs& f, hipStream_t st);
 

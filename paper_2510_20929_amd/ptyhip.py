@@ -47,12 +47,12 @@ class Desc(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32), ("device_atomics", ctypes.c_int32)]
+                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_size_t), ("scratch_bytes", ctypes.c_size_t),
-                ("plain_bytes", ctypes.c_size_t), ("grid", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("window_bytes", ctypes.c_size_t), ("plain_bytes", ctypes.c_size_t), ("grid", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("fused_on_chip", ctypes.c_int32), ("plain_chunk", ctypes.c_int32)]
 
 
@@ -162,8 +162,7 @@ class Plan:
         h = ctypes.c_void_p()
         if tune:
             tu = Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)),
-                      int(tune.get("recompute", 0)), int(tune.get("plain_chunk", 0)),
-                      int(tune.get("device_atomics", 0)))
+                      int(tune.get("recompute", 0)), int(tune.get("plain_chunk", 0)))
             st = _lib().ptyhip_plan_create_ex(ctypes.byref(self.desc), self.max_positions, ctypes.byref(tu),
                                               ctypes.byref(h))
         else:
