@@ -118,8 +118,11 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   } else {
     p->threads = 256;
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
+    p->big_fused_ready = S == 1;
   }
-  int grid = p->tune.grid > 0 ? p->tune.grid : p->cus;
+  // persistent grid: one workgroup per CU (the on-chip kernel fills a CU's LDS); two
+  // for 256^2 frames, whose LDS tiles leave room for a second workgroup
+  int grid = p->tune.grid > 0 ? p->tune.grid : (N == 256 ? 2 * p->cus : p->cus);
   p->grid = grid;
   if (p->scratch_stride > 0) {
     if ((st = dalloc(p, &p->scratch, p->scratch_stride * size_t(grid))) != PTYHIP_OK) return st;

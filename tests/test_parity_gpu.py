@@ -64,3 +64,24 @@ def test_amplitude_weights_single_eigenprobe(plain):
     ref = run_oracle(start, I, grads)
     got = run_gpu(_plan(start), start, I, grads, plain=plain)
     compare(got, ref, grads, tag=f"amp-weights {'plain' if plain else 'fused'}")
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_config2_reduced(plain):
+    """Config 2 structure (256^2 frames, 8 orthogonalised eigenprobes, per-position OPR
+    weights, jittered raster, amplitude loss) on a 700^2 object with 300 positions."""
+    start, I = case(2, H=700, K=300)
+    grads = ("obj", "probe", "weights", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"c2 {'plain' if plain else 'fused'}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_frame512(plain):
+    start, I = custom_problem(512, 512, 2, 1, 1, 700, 14, loss="poisson", weights="amp")
+    grads = ("obj", "probe", "pos", "weights")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"N=512 {'plain' if plain else 'fused'}")
