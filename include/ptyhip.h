@@ -71,7 +71,8 @@ enum {
   PTYHIP_GRAD_POS = 4,      /* position gradient             [K][2] float */
   PTYHIP_GRAD_WEIGHTS = 8,  /* OPR weight gradient           [K][E] float */
   PTYHIP_ACCUMULATE = 16,   /* add into the outputs (and loss) instead of overwriting */
-  PTYHIP_PLAIN = 32         /* run the per-step kernels instead of the fused kernel */
+  PTYHIP_PLAIN = 32,        /* run the per-step kernels instead of the fused kernel */
+  PTYHIP_BATCH_PER_CALL = 64 /* batch only: one non-captured fused call per dataset */
 };
 
 /* bits of the device error latch */
@@ -180,9 +181,13 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
 ptyhip_status ptyhip_batch_bind(ptyhip_batch b, int32_t i, const float* obj, const float* probe,
                                 const float* weights, const float* positions, const float* I_meas, double* loss,
                                 float* g_obj, float* g_probe, float* g_pos, float* g_weights);
-/* Run every dataset (flags as in ptyhip_forward_adjoint; PTYHIP_PLAIN runs one
- * non-captured per-dataset call each instead). The first call with given flags captures
- * a graph on `stream`; later calls replay it. */
+/* Run every dataset (gradient flags as in ptyhip_forward_adjoint; outputs are
+ * overwritten). By default all datasets run in one persistent launch whose workgroups
+ * are split among the datasets in proportion to their work, followed by per-dataset
+ * reductions; the first launch with given flags captures this into a hipGraph on
+ * `stream` and later launches replay it. PTYHIP_BATCH_PER_CALL runs one non-captured
+ * fused call per dataset instead, PTYHIP_PLAIN one per-step call per dataset. Frame
+ * sizes 64, 128, 256 and 512, one slice. */
 ptyhip_status ptyhip_batch_launch(ptyhip_batch b, void* stream, uint32_t flags);
 ptyhip_status ptyhip_batch_get_error(ptyhip_batch b, void* stream, uint32_t* flags);
 void ptyhip_batch_destroy(ptyhip_batch b);

@@ -5,8 +5,10 @@ forms. Importing the package does not load the library; the first call does, and
 fails loudly if it has not been built.
 """
 from .ptyhip import (  # noqa: F401
-    ACCUMULATE, FLAG_BOUNDS, FLAG_NONFINITE, GRAD_OBJ, GRAD_POS, GRAD_PROBE, GRAD_WEIGHTS, LOSS_AMPLITUDE,
+    ACCUMULATE, BATCH_PER_CALL, Batch, FLAG_BOUNDS, FLAG_NONFINITE, GRAD_OBJ, GRAD_POS, GRAD_PROBE, GRAD_WEIGHTS, LOSS_AMPLITUDE,
     LOSS_POISSON, PLAIN, Desc, Plan, PtyhipError, lib, make_desc, ptyhip_desc_validate,
 )
 
-__all__ = ["Plan", "PtyhipError", "make_desc", "ptyhip_desc_validate", "lib"]
+from .autograd import PtychoLoss, ptycho_loss  # noqa: F401,E402
+
+__all__ = ["Plan", "PtyhipError", "PtychoLoss", "make_desc", "ptycho_loss", "ptyhip_desc_validate", "lib"]

@@ -1,0 +1,180 @@
+"""Autotuner for the fused forward + adjoint and the batched launch.
+
+For a problem shape it enumerates implementation choices (thread layout of the
+on-chip kernel, storing vs recomputing far fields / incident waves, persistent grid
+size; for batches the total workgroup count, or one call per dataset), runs every
+candidate once and keeps it only if its loss and gradients agree with the per-step
+form on the same inputs (forward <= 1e-5, gradients <= 1e-4 relative L2), then times
+the survivors with HIP events (median of several launches) and caches the fastest
+in a JSON file keyed by GPU architecture and problem shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+from .ptyhip import Batch, Plan
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def _arch() -> str:
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _cus() -> int:
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def shape_key(N, M, E, S, loss, grads: Sequence[str], K: int) -> str:
+    kb = 1 << max(0, int(K - 1).bit_length())  # bucket positions by power of two
+    return f"{_arch()}|N{N}|M{M}|E{E}|S{S}|{loss}|{'+'.join(sorted(grads))}|K{kb}"
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def plan_candidates(N: int, M: int, S: int) -> List[dict]:
+    cus = _cus()
+    out = []
+    variants = [0, 1] if N in (64, 128) else [0]
+    recomputes = [0, 1] if (M > 1 or S > 1) else [0]
+    grids = [0, 2 * cus] if N <= 128 else [0, cus if N == 256 else 2 * cus]
+    for v in variants:
+        for r in recomputes:
+            for g in grids:
+                out.append({"variant": v, "recompute": r, "grid": g})
+    return out
+
+
+def _rel(a: torch.Tensor, b: torch.Tensor) -> float:
+    a = torch.view_as_real(a) if a.is_complex() else a
+    b = torch.view_as_real(b) if b.is_complex() else b
+    return float((a.double() - b.double()).norm() / b.double().norm().clamp_min(1e-300))
+
+
+def _agrees(out: dict, ref: dict, grads: Sequence[str]) -> Optional[str]:
+    e = abs(float(out["loss"][0]) - float(ref["loss"][0])) / max(abs(float(ref["loss"][0])), 1e-300)
+    if not e <= FWD_TOL:
+        return f"loss {e:.2e}"
+    for g in grads:
+        key = {"obj": "g_obj", "probe": "g_probe", "pos": "g_pos", "weights": "g_weights"}[g]
+        r = _rel(out[key], ref[key])
+        if not r <= GRAD_TOL:
+            return f"{key} {r:.2e}"
+    return None
+
+
+def _time(fn, reps: int) -> float:
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("obj", "probe", "pos"),
+              reps: int = 5, cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True, log=None):
+    """Pick the fastest parity-passing fused configuration for one plan shape.
+    ``shape`` holds N, M, E, S, H, W, loss, eps, lambda_z. Returns (tune, report)."""
+    K = int(positions.shape[0])
+    key = shape_key(shape["N"], shape["M"], shape["E"], shape["S"], shape["loss"], grads, K)
+    cache = load_cache(cache_path) if (cache_path and use_cache) else {}
+    if use_cache and key in cache:
+        return cache[key]["tune"], {"key": key, "cached": True}
+
+    def make(tune):
+        return Plan(shape["N"], shape["M"], shape["E"], shape["S"], shape["H"], shape["W"], shape["loss"],
+                    shape.get("eps", 1e-3), shape.get("lambda_z", 0.0), 0.0, K, tune)
+
+    ref_plan = make(None)
+    ref = ref_plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads, plain=True)
+    torch.cuda.synchronize()
+    del ref_plan
+    results = []
+    best = None
+    for cand in plan_candidates(shape["N"], shape["M"], shape["S"]):
+        plan = make(cand)
+        out = plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads)
+        torch.cuda.synchronize()
+        bad = _agrees(out, ref, grads)
+        if bad:
+            results.append({"tune": cand, "parity": bad})
+            continue
+        ms = _time(lambda: plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads,
+                                                out=out), reps)
+        results.append({"tune": cand, "ms": ms})
+        if log:
+            log(f"tune {cand}: {ms:.3f} ms")
+        if best is None or ms < best[1]:
+            best = (cand, ms)
+        del plan
+    if best is None:
+        raise RuntimeError(f"no autotuner candidate passed parity for {key}: {results}")
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[key] = {"tune": best[0], "ms": best[1], "when": time.strftime("%Y-%m-%d %H:%M:%S"),
+                      "candidates": results}
+        save_cache(cache, cache_path)
+    return best[0], {"key": key, "cached": False, "candidates": results}
+
+
+def tune_batch(problems, tensors, grads=("obj", "probe", "pos"), reps: int = 3, log=None):
+    """Pick the total workgroup count of the batched launch (or one call per dataset).
+    ``tensors[i]`` = (obj, probe, positions, I_meas, weights) on the device. Every
+    candidate must reproduce the per-call results of each dataset. Returns (choice, report)."""
+    cus = _cus()
+    ref_b = Batch(problems)
+    refs = [ref_b.bind(i, *t[:4], weights=t[4]) for i, t in enumerate(tensors)]
+    ref_b.launch(grads, per_call=True)
+    torch.cuda.synchronize()
+    ref = [{k: v.clone() for k, v in r.items()} for r in refs]
+    results = []
+    best = None
+    for total in (cus, 2 * cus, 4 * cus):
+        b = Batch(problems, tune={"grid": total})
+        outs = [b.bind(i, *t[:4], weights=t[4]) for i, t in enumerate(tensors)]
+        b.launch(grads)
+        torch.cuda.synchronize()
+        bad = None
+        for i, o in enumerate(outs):
+            bad = bad or _agrees(o, ref[i], grads)
+        if bad:
+            results.append({"grid": total, "parity": bad})
+            continue
+        ms = _time(lambda: b.launch(grads), reps)
+        results.append({"grid": total, "ms": ms})
+        if log:
+            log(f"batch grid {total}: {ms:.3f} ms")
+        if best is None or ms < best[1]:
+            best = ({"grid": total}, ms)
+    ms = _time(lambda: ref_b.launch(grads, per_call=True), reps)
+    results.append({"per_call": True, "ms": ms})
+    if best is None or ms < best[1]:
+        best = ({"per_call": True}, ms)
+    return best[0], {"candidates": results}

@@ -132,6 +132,7 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   const size_t win = size_t(S) * (N + 1) * (N + 1) * sizeof(float2);
   const size_t win_budget = size_t(2) << 30;
   p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(maxK, 1)), win_budget / win)));
+  if (p->whole_windows) p->fchunk = std::max(maxK, 1);
   if ((st = dalloc(p, &p->gwin, size_t(p->fchunk) * S * (N + 1) * (N + 1))) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->wvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
   p->window_bytes = size_t(p->fchunk) * win;
@@ -176,7 +177,7 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
 // Build the kernel argument block of one call.
 static bool uses_fused(const Plan* p, bool plain) { return !plain && (p->on_chip || p->big_fused_ready); }
 
-static CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj, const float* probe,
+CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj, const float* probe,
                           const float* weights, const float* positions, const float* I_meas, const float* Y,
                           float* Psi, float* I_pred, float* g_obj, bool want_probe, bool want_pos, bool want_w) {
   const ptyhip_desc& d = p->d;

@@ -38,6 +38,7 @@ struct Plan {
   float2* gwin = nullptr;    // [fchunk][S][N+1][N+1] window gradients
   int* wvalid = nullptr;     // [fchunk]
   size_t window_bytes = 0;
+  bool whole_windows = false;  // window buffer for every position (batched launches)
   size_t scratch_stride = 0;
   size_t scratch_bytes = 0;
   // per-step form
@@ -63,6 +64,9 @@ struct Plan {
 bool is_supported_frame(int n);
 ptyhip_status validate_desc(const ptyhip_desc* d);
 ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tune* tune);
+CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj, const float* probe,
+                   const float* weights, const float* positions, const float* I_meas, const float* Y, float* Psi,
+                   float* I_pred, float* g_obj, bool want_probe, bool want_pos, bool want_w);
 ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
                                    const float* probe, const float* weights, const float* positions,
                                    const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,

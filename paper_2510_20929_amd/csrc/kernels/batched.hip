@@ -1,0 +1,115 @@
+// Many independent reconstructions of uneven frame size in one persistent launch.
+//
+// The launch's workgroups are partitioned among the datasets in proportion to their
+// work (positions x modes x transform cost); every workgroup reads its dataset's call
+// arguments from a device descriptor table and runs the same per-position body as
+// the per-plan kernels (512 threads: on-chip transforms for 64^2 and 128^2, scratch-
+// resident four-step transforms for 256^2 and 512^2). Gather, probe reduction and
+// final reductions follow per dataset; they too read their pointers from the table,
+// so a captured graph stays valid when the caller rebinds buffers.
+#include "big_body.hpp"
+#include "gather.hpp"
+#include "launch.hpp"
+#include "small_body.hpp"
+
+namespace ptyhip {
+
+constexpr int BT = 512;
+
+union BatchShared {
+  SmallShared<64, BT> s64;
+  SmallShared<128, BT> s128;
+  BigShared<256, BT> b256;
+  BigShared<512, BT> b512;
+};
+
+__global__ __launch_bounds__(BT) void batched_kernel(const BatchEntry* __restrict__ tab, int n) {
+  __shared__ BatchShared sh;
+  int d = 0;
+  while (d + 1 < n && int(blockIdx.x) >= tab[d + 1].first_wg) ++d;
+  const CallArgs a = tab[d].a;
+  const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
+  switch (tab[d].N * 2 + a.loss) {
+    case 128: small_body<64, BT, 0>(a, sh.s64, wg, nwg); break;
+    case 129: small_body<64, BT, 1>(a, sh.s64, wg, nwg); break;
+    case 256: small_body<128, BT, 0>(a, sh.s128, wg, nwg); break;
+    case 257: small_body<128, BT, 1>(a, sh.s128, wg, nwg); break;
+    case 512: big_body<256, BT, 0>(a, sh.b256, wg, nwg); break;
+    case 513: big_body<256, BT, 1>(a, sh.b256, wg, nwg); break;
+    case 1024: big_body<512, BT, 0>(a, sh.b512, wg, nwg); break;
+    case 1025: big_body<512, BT, 1>(a, sh.b512, wg, nwg); break;
+    default: break;
+  }
+}
+
+size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off) {
+  if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, 0, pacc_off);
+  return big_scratch_elems(N, M, E, pacc_off);
+}
+
+__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchEntry* __restrict__ tab, int d) {
+  gather_tile(tab[d].g);
+}
+
+// probe gradient of dataset d: sum of its workgroups' accumulators; the on-chip bodies
+// store element i of thread t at i*T + t, the four-step bodies in natural order
+template <int N>
+__global__ void batch_probe_reduce_kernel(const BatchEntry* __restrict__ tab, int d) {
+  const CallArgs& a = tab[d].a;
+  float2* out = tab[d].g_probe;
+  const int groups = tab[d].n_wg;
+  constexpr size_t NN = size_t(N) * N;
+  const size_t n = size_t(a.E) * a.M * NN;
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += size_t(gridDim.x) * blockDim.x) {
+    const size_t em = g / NN, r = g % NN;
+    const float2* src = a.scratch + a.pacc_off + em * NN + r;
+    float2 s = make_float2(0.f, 0.f);
+    for (int w = 0; w < groups; ++w) s = cadd(s, src[size_t(w) * a.scratch_stride]);
+    size_t pix = r;
+    if constexpr (N <= 128) pix = size_t(SmallCtx<N, BT>::a_pix(int(r % BT), int(r / BT)));
+    out[em * NN + pix] = s;
+  }
+}
+
+// loss, position and weight gradients of dataset d
+__global__ __launch_bounds__(1024) void batch_finalize_kernel(const BatchEntry* __restrict__ tab, int d) {
+  __shared__ double red[1024 / WAVE];
+  const CallArgs& a = tab[d].a;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < a.K; k += 1024) s += a.loss_part[k];
+  s = block_sum<1024>(s, red);
+  if (threadIdx.x == 0 && tab[d].loss) *tab[d].loss = s;
+  if (tab[d].g_pos && a.pos_part)
+    for (int i = threadIdx.x; i < 2 * a.K; i += 1024) tab[d].g_pos[i] = float(a.pos_part[i]);
+  if (tab[d].g_w && a.w_part)
+    for (int i = threadIdx.x; i < a.E * a.K; i += 1024) tab[d].g_w[i] = float(a.w_part[i]);
+}
+
+hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, int total_wg,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(batched_kernel, dim3(total_wg), dim3(BT), 0, st, dev_tab, n);
+  for (int d = 0; d < n; ++d) {
+    const BatchEntry& e = host_tab[d];
+    if (e.a.mode != MODE_FWD_ADJ) continue;
+    if (e.g.gobj) {
+      dim3 grid(unsigned((e.g.W + GT - 1) / GT), unsigned((e.g.H + GT - 1) / GT), unsigned(e.g.S));
+      hipLaunchKernelGGL(batch_gather_kernel, grid, dim3(256), 0, st, dev_tab, d);
+    }
+    if (e.g_probe) {
+      const size_t nel = size_t(e.a.E) * e.a.M * e.N * e.N;
+      size_t blocks = (nel + 255) / 256;
+      if (blocks > 4096) blocks = 4096;
+      switch (e.N) {
+        case 64: hipLaunchKernelGGL(batch_probe_reduce_kernel<64>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
+        case 128: hipLaunchKernelGGL(batch_probe_reduce_kernel<128>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
+        case 256: hipLaunchKernelGGL(batch_probe_reduce_kernel<256>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
+        case 512: hipLaunchKernelGGL(batch_probe_reduce_kernel<512>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  for (int d = 0; d < n; ++d) hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, st, dev_tab, d);
+  return hipGetLastError();
+}
+
+}  // namespace ptyhip

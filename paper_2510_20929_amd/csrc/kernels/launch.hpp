@@ -63,4 +63,22 @@ hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g
 
 hipError_t launch_finalize(const FinalArgs& f, hipStream_t st);
 
+// One dataset of a batched launch, as the device reads it from the descriptor table.
+struct BatchEntry {
+  CallArgs a;        // call arguments of the dataset (whole position range)
+  GatherArgs g;      // window gather into the object gradient
+  float2* g_probe;   // probe gradient output or nullptr
+  double* loss;      // loss output
+  float* g_pos;      // position gradient output or nullptr
+  float* g_w;        // weight gradient output or nullptr
+  int first_wg;      // first workgroup of the dataset in the batched launch
+  int n_wg;          // workgroups assigned to the dataset
+  int N;             // frame size
+  int pad;
+};
+
+size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off);
+hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, int total_wg,
+                          hipStream_t st);
+
 }  // namespace ptyhip

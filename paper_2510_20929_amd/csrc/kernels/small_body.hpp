@@ -1,0 +1,355 @@
+// Per-position bodies of the fused forward + adjoint for on-chip frames (N <= 128),
+// shared by the per-plan kernels and the batched kernel.
+//
+// One workgroup owns one scan position at a time (positions are strided over a
+// persistent grid, so the workgroups in flight cover a compact stretch of the scan
+// and share object rows in L2). For each position it
+//   gathers the bilinear object patch,
+//   forms each mode's exit wave, transforms it (registers + LDS), sums |Psi|^2,
+//   evaluates the loss against the measured pattern and dl/dI,
+//   scales each mode's far field by 2 dl/dI / (K_norm N^2) and transforms back,
+//   forms the patch gradient sum_m conj(P_m) g_m and the probe gradient conj(o) g_m,
+//   and finally builds the (N+1)^2 object-window gradient in LDS from the patch
+//   gradient (the transpose of the bilinear gather) and reduces the position gradient.
+//
+// No atomics: float atomics are the scarce resource on this path. Each workgroup
+// accumulates its probe gradient in its own scratch slice (plain read-modify-write),
+// and each position's window gradient is written to a window buffer; small follow-up
+// kernels sum the slices and gather the windows into the object gradient in a fixed
+// order, so the gradients are bitwise reproducible.
+// Multislice: incident waves and patches of every slice live in the workgroup
+// scratch (L2/MALL resident), or the incident waves are recomputed.
+#pragma once
+#include "../device/fft.hpp"
+#include "../device/model.hpp"
+#include "args.hpp"
+
+namespace ptyhip {
+
+constexpr int MAX_EIG = 16;
+
+template <int N, int T>
+struct SmallCtx {
+  using F = Frame2D<N, T>;
+  static constexpr int E = F::E;
+  static constexpr int L = F::L;
+  static constexpr int N2 = F::N2;
+  static constexpr int NN = N * N;
+  static constexpr int WN = N + 1;  // window side
+  __device__ __forceinline__ static int a_pix(int t, int i) {
+    const int l = i / N2, j = i % N2;
+    return F::a_y(t, l) * N + F::a_x(t, l, j);
+  }
+  __device__ __forceinline__ static int d_freq(int t, int i) {
+    const int l = i / N2, ii = i % N2;
+    return F::d_ky(t, l, ii) * N + F::d_kx(t, l);
+  }
+  __device__ __forceinline__ static int d_centred(int t, int i) {
+    const int l = i / N2, ii = i % N2;
+    return centred_index(F::d_ky(t, l, ii), F::d_kx(t, l), N);
+  }
+};
+
+// Zero every per-position output of an invalid position and latch the error.
+template <int N, int T>
+__device__ __forceinline__ void skip_position(const CallArgs& a, int k, const PosInfo& p) {
+  constexpr int NN = N * N;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
+    if (a.loss_part) a.loss_part[k] = 0.0;
+    if (a.pos_part) {
+      a.pos_part[2 * k] = 0.0;
+      a.pos_part[2 * k + 1] = 0.0;
+    }
+    if (a.wvalid) a.wvalid[k] = 0;
+  }
+  if (a.w_part && tid < a.E) a.w_part[size_t(k) * a.E + tid] = 0.0;
+  if (a.ipred)
+    for (int i = tid; i < NN; i += T) a.ipred[size_t(k) * NN + i] = 0.f;
+  if (a.mode == MODE_APPLY_A)
+    for (int i = tid; i < a.M * NN; i += T) a.psi_out[size_t(k) * a.M * NN + i] = make_float2(0.f, 0.f);
+}
+
+// Loss of one position from the incoherent sum held in layout D; on return Iacc holds
+// dl/dI. Returns false if the position's loss is not finite (then it is skipped).
+template <int N, int T, int LOSS>
+__device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&Iacc)[Frame2D<N, T>::E],
+                                              double* red) {
+  using C = SmallCtx<N, T>;
+  const float* im = a.imeas + size_t(k) * C::NN;
+  const int t = opaque_tid();
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < C::E; ++i) {
+    const int ci = C::d_centred(t, i);
+    float l, c;
+    loss_terms<LOSS>(Iacc[i], im[ci], a.eps, l, c);
+    if (a.ipred) a.ipred[size_t(k) * C::NN + ci] = Iacc[i];
+    lsum += double(l);
+    Iacc[i] = c;
+  }
+  const double tot = block_sum<T>(lsum, red);
+  const bool fin = isfinite(tot);
+  if (threadIdx.x == 0) {
+    a.loss_part[k] = fin ? tot * double(a.lscale) : 0.0;
+    if (!fin) {
+      latch(a.flags, FLAG_NONFINITE);
+      if (a.pos_part) {
+        a.pos_part[2 * k] = 0.0;
+        a.pos_part[2 * k + 1] = 0.0;
+      }
+      if (a.wvalid) a.wvalid[k] = 0;
+    }
+  }
+  if (!fin && a.w_part && int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = 0.0;
+  return fin;
+}
+
+// Zero this workgroup's probe-gradient accumulator ([E][M] scratch frames).
+template <int N, int T>
+__device__ __forceinline__ void zero_probe_acc(const CallArgs& a, float2* acc) {
+  const size_t n = size_t(a.E) * a.M * N * N;
+  for (size_t i = threadIdx.x; i < n; i += T) acc[i] = make_float2(0.f, 0.f);
+}
+
+// Probe-side gradients of one mode from the gradient gP of the incident probe wave
+// (layout A): accumulate w_e gP into the workgroup's accumulator frames, and the
+// OPR weight-gradient sums Re<gP, U_e,m>.
+template <int N, int T>
+__device__ __forceinline__ void probe_gradients(const CallArgs& a, int m, const float* wk,
+                                                const float2 (&gP)[Frame2D<N, T>::E], float2* acc, double* red,
+                                                double* wacc) {
+  using C = SmallCtx<N, T>;
+  const int t = opaque_tid();
+  if ((a.want & WANT_PROBE) && acc) {
+    const int ne = wk ? a.E : 1;
+    for (int e = 0; e < ne; ++e) {
+      float2* fr = acc + (size_t(e) * a.M + m) * C::NN;
+      const float w = wk ? wk[e] : 1.f;
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) {
+        const size_t si = size_t(i) * T + t;
+        float2 g = fr[si];
+        g.x = fmaf(w, gP[i].x, g.x);
+        g.y = fmaf(w, gP[i].y, g.y);
+        fr[si] = g;
+      }
+    }
+  }
+  if ((a.want & WANT_WEIGHTS) && wk != nullptr) {
+    for (int e = 0; e < a.E; ++e) {
+      const float2* U = a.probe + (size_t(e) * a.M + m) * C::NN;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < C::E; ++i) s += double(cdotre(gP[i], U[C::a_pix(t, i)]));
+      s = block_sum<T>(s, red);
+      if (threadIdx.x == 0) wacc[e] += s;
+    }
+  }
+}
+
+// Object-window pass for one slice: LDS holds the patch gradient in natural order.
+// Writes the bilinear-transposed (N+1)^2 window gradient and accumulates the position
+// gradient (which reads the object window; requested only with a full window).
+template <int N, int T>
+__device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p, const float2* lds,
+                                           const float2* __restrict__ Os, float2* gwin, double& gy, double& gx) {
+  constexpr int P = Frame2D<N, T>::P;
+  constexpr int WN = N + 1;
+  const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
+  const float w10 = p.fy * (1.f - p.fx), w11 = p.fy * p.fx;
+  const bool want_obj = (a.want & WANT_OBJ) && gwin != nullptr;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const float2 z = make_float2(0.f, 0.f);
+  for (int idx = threadIdx.x; idx < WN * WN; idx += T) {
+    const int py = idx / WN, px = idx - py * WN;
+    const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
+    const float2 g00 = (iy0 && ix0) ? lds[py * P + px] : z;
+    const float2 g01 = (iy0 && ix1) ? lds[py * P + px - 1] : z;
+    const float2 g10 = (iy1 && ix0) ? lds[(py - 1) * P + px] : z;
+    const float2 g11 = (iy1 && ix1) ? lds[(py - 1) * P + px - 1] : z;
+    if (want_obj) {
+      float2 g;
+      g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
+      g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
+      gwin[idx] = g;
+    }
+    if (want_pos) {
+      const float2 A = Os[size_t(p.y0 + py) * a.W + (p.x0 + px)];
+      float2 hy, hx;
+      hy.x = (1.f - p.fx) * (g10.x - g00.x) + p.fx * (g11.x - g01.x);
+      hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
+      hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
+      hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
+      gy += double(cdotre(hy, A));
+      gx += double(cdotre(hx, A));
+    }
+  }
+}
+
+template <int N, int T>
+__device__ __forceinline__ void finish_position(const CallArgs& a, int k, double gy, double gx, double* red,
+                                                const double* wacc) {
+  if ((a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && a.pos_part) {
+    double v[2] = {gy, gx};
+    block_sum_n<T, 2>(v, red);
+    if (threadIdx.x == 0) {
+      a.pos_part[2 * k] = v[0];
+      a.pos_part[2 * k + 1] = v[1];
+    }
+  }
+  if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights) {
+    __syncthreads();
+    if (int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = wacc[threadIdx.x];
+  }
+  if (threadIdx.x == 0 && a.wvalid) a.wvalid[k] = 1;
+}
+
+// ----------------------------------------------------------------------------- single slice
+// Registers hold only the working frame v and dl/dI (3 E floats per thread). The
+// workgroup's scratch ([E][T] frames, coalesced) holds the patch o, the running patch
+// gradient sum_m conj(P_m) g_m (several modes), the far fields of all but the last
+// mode (unless they are recomputed), and the probe-gradient accumulator.
+// LDS the body needs (the caller owns it so that one kernel can host several bodies)
+template <int N, int T>
+struct SmallShared {
+  float2 lds[Frame2D<N, T>::LDS_ELEMS];
+  float2 tws[N];
+  double red[2 * (T / WAVE)];
+  float wsh[MAX_EIG];
+  double wacc[MAX_EIG];
+};
+
+// Workgroup `wg` of `nwg` processes positions wg, wg + nwg, ... of the call `a`.
+template <int N, int T, int LOSS>
+__device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>& sh, int wg, int nwg) {
+  using F = Frame2D<N, T>;
+  using C = SmallCtx<N, T>;
+  constexpr int E = C::E;
+  float2* lds = sh.lds;
+  float2* tws = sh.tws;
+  double* red = sh.red;
+  float* wsh = sh.wsh;
+  double* wacc = sh.wacc;
+  const float inv_n = 1.f / float(N);
+  const bool fwd = a.mode != MODE_APPLY_AH;
+  const bool adj = a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
+  // scratch: patch [NN], patch-gradient accumulator [NN], far fields of modes 0..M-2,
+  // probe-gradient accumulator [E][M][NN]
+  float2* obuf = a.scratch + size_t(wg) * a.scratch_stride;
+  float2* gacc = obuf + size_t(C::NN);
+  float2* psis = gacc + size_t(C::NN);
+  float2* pacc = obuf + a.pacc_off;
+  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
+
+  for (int k = wg; k < a.K; k += nwg) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) {
+      skip_position<N, T>(a, k, p);
+      continue;
+    }
+    __syncthreads();
+    if (a.weights && int(threadIdx.x) < a.E) wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
+    if (threadIdx.x < MAX_EIG) wacc[threadIdx.x] = 0.0;
+    __syncthreads();
+    const float* wk = a.weights ? wsh : nullptr;
+
+    {
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = i / C::N2, j = i % C::N2;
+        obuf[size_t(i) * T + t] = bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
+      }
+    }
+
+    float2 v[E];
+    float cf[E];
+    if (fwd) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cf[i] = 0.f;
+      for (int m = 0; m < a.M; ++m) {
+        {
+          const int t = opaque_tid();
+#pragma unroll
+          for (int i = 0; i < E; ++i)
+            v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+        }
+        F::forward(v, lds, tws, inv_n);
+#pragma unroll
+        for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
+        if (m < a.M - 1 && a.mode == MODE_FWD_ADJ && !a.recompute) {
+          // keep this mode's far field for the adjoint (the last one stays in registers)
+          const int t = opaque_tid();
+          float2* ps = psis + size_t(m) * C::NN;
+#pragma unroll
+          for (int i = 0; i < E; ++i) ps[size_t(i) * T + t] = v[i];
+        }
+        if (a.mode == MODE_APPLY_A) {
+          const int t = opaque_tid();
+          float2* out = a.psi_out + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+          for (int i = 0; i < E; ++i) out[C::d_freq(t, i)] = v[i];
+        }
+      }
+      if (a.mode == MODE_APPLY_A) continue;
+      if (!position_loss<N, T, LOSS>(a, k, cf, red)) continue;
+      if (a.mode == MODE_FORWARD) continue;
+    }
+
+    // adjoint, last mode first (its far field is still in registers)
+    for (int mm = 0; mm < a.M; ++mm) {
+      const int m = a.M - 1 - mm;
+      if (!fwd) {
+        const int t = opaque_tid();
+        const float2* y = a.Y + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = y[C::d_freq(t, i)];
+      } else {
+        if (mm > 0) {
+          const int t = opaque_tid();
+          if (a.recompute) {
+            // recompute this mode's far field instead of reading it back
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+              v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+            F::forward(v, lds, tws, inv_n);
+          } else {
+            const float2* ps = psis + size_t(m) * C::NN;
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
+      }
+      F::inverse(v, lds, tws, inv_n);
+      const bool last = mm == a.M - 1;
+      __syncthreads();  // every thread is done reading LDS before the patch gradient lands there
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int pix = C::a_pix(t, i);
+          float2 go = cmulc(probe_at(a.probe, wk, a.E, a.M, C::NN, m, pix), v[i]);
+          const size_t si = size_t(i) * T + t;
+          if (mm > 0) go = cadd(go, gacc[si]);
+          if (last) lds[(pix / N) * F::P + (pix % N)] = go;
+          else gacc[si] = go;
+          v[i] = cmulc(obuf[si], v[i]);
+        }
+      }
+      probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);
+    }
+
+    __syncthreads();
+    double gy = 0.0, gx = 0.0;
+    window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);
+    finish_position<N, T>(a, k, gy, gx, red, wacc);
+  }
+}
+
+}  // namespace ptyhip

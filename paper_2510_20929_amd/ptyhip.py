@@ -295,3 +295,71 @@ class Plan:
 
     def clear_error(self, stream=None):
         _check(_lib().ptyhip_clear_error(self._h, _stream(stream)), "ptyhip_clear_error")
+
+
+BATCH_PER_CALL = 64
+
+
+class Batch:
+    """Many independent datasets (uneven frame sizes) run together: one persistent
+    launch captured in a hipGraph (default), or one call per dataset."""
+
+    def __init__(self, problems, tune: Optional[dict] = None):
+        descs = (Desc * len(problems))(*[make_desc(p.N, p.M, p.E, p.S, p.H, p.W, p.loss, p.eps, p.lambda_z)
+                                        for p in problems])
+        Ks = (_i32 * len(problems))(*[int(p.K) for p in problems])
+        h = ctypes.c_void_p()
+        tu = None
+        if tune:
+            tu = ctypes.byref(Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)), int(tune.get("recompute", 0)),
+                                   int(tune.get("plain_chunk", 0))))
+        _check(_lib().ptyhip_batch_create(descs, Ks, len(problems), tu, ctypes.byref(h)), "ptyhip_batch_create")
+        self._h = h
+        self.n = len(problems)
+        self.shapes = [(p.N, p.M, p.E, p.S, p.H, p.W, p.K) for p in problems]
+        self._keep = [None] * self.n
+
+    def bind(self, i, obj, probe, positions, I_meas, weights=None, out: Optional[dict] = None):
+        """Bind dataset i's device tensors; returns the output dict (allocated if absent)."""
+        N, M, E, S, H, W, K = self.shapes[i]
+        dev = obj.device
+        out = dict(out or {})
+        out.setdefault("loss", torch.zeros(1, dtype=torch.float64, device=dev))
+        out.setdefault("g_obj", torch.zeros((S, H, W), dtype=torch.complex64, device=dev))
+        out.setdefault("g_probe", torch.zeros((E, M, N, N), dtype=torch.complex64, device=dev))
+        out.setdefault("g_pos", torch.zeros((K, 2), dtype=torch.float32, device=dev))
+        if weights is not None:
+            out.setdefault("g_weights", torch.zeros((K, E), dtype=torch.float32, device=dev))
+        st = _lib().ptyhip_batch_bind(self._h, i, _ptr(obj), _ptr(probe), _ptr(weights), _ptr(positions),
+                                      _ptr(I_meas), _ptr(out["loss"]), _ptr(out["g_obj"]), _ptr(out["g_probe"]),
+                                      _ptr(out["g_pos"]), _ptr(out.get("g_weights")))
+        _check(st, "ptyhip_batch_bind")
+        self._keep[i] = (obj, probe, positions, I_meas, weights, out)
+        return out
+
+    def launch(self, grads=("obj", "probe", "pos"), per_call=False, plain=False, stream=None):
+        flags = 0
+        for g, f in (("obj", GRAD_OBJ), ("probe", GRAD_PROBE), ("pos", GRAD_POS), ("weights", GRAD_WEIGHTS)):
+            if g in grads:
+                flags |= f
+        if per_call:
+            flags |= BATCH_PER_CALL
+        if plain:
+            flags |= PLAIN
+        _check(_lib().ptyhip_batch_launch(self._h, _stream(stream), flags), "ptyhip_batch_launch")
+
+    def get_error(self, stream=None) -> int:
+        f = ctypes.c_uint32(0)
+        _check(_lib().ptyhip_batch_get_error(self._h, _stream(stream), ctypes.byref(f)), "ptyhip_batch_get_error")
+        return int(f.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().ptyhip_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
