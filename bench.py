@@ -27,6 +27,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published)
 
 KERNEL_SOURCES = [
     "paper_2510_20929_amd/csrc/kernels/fused_small.hip",
+    "paper_2510_20929_amd/csrc/kernels/small_body.hpp",
     "paper_2510_20929_amd/csrc/device/fft.hpp",
     "paper_2510_20929_amd/csrc/device/model.hpp",
     "paper_2510_20929_amd/csrc/device/common.hpp",
@@ -110,6 +111,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-step form")
+    ap.add_argument("--tune", default=None,
+                    help="fixed implementation choice as JSON (skips the autotuner; used for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration for the PMC runs)")
     args = ap.parse_args()
@@ -139,14 +142,26 @@ def main():
     start = W.perturb(truth, 21)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     obj, probe, pos = t(start.obj), t(start.probe), t(start.positions)
-    plan = Plan.for_problem(start)
+    base = Plan.for_problem(start)
     # measured intensities: the clean far field of the truth (computed by the library) plus Poisson noise
     I_clean = torch.empty((truth.K, truth.N, truth.N), dtype=torch.float32, device=dev)
-    plan.forward(t(truth.obj), t(truth.probe), t(truth.positions), torch.zeros_like(I_clean), I_pred=I_clean)
+    base.forward(t(truth.obj), t(truth.probe), t(truth.positions), torch.zeros_like(I_clean), I_pred=I_clean)
     gen = torch.Generator(device=dev)
     gen.manual_seed(20931)
     I_meas = torch.poisson(I_clean, generator=gen).contiguous()
     grads = ("obj", "probe", "pos")
+    del base
+    # implementation choice by the autotuner (parity-gated, untimed here)
+    from paper_2510_20929_amd import autotune
+    shape = dict(N=start.N, M=start.M, E=start.E, S=start.S, H=start.H, W=start.W, loss=start.loss, eps=start.eps,
+                 lambda_z=start.lambda_z)
+    cache = os.environ.get("PTYHIP_TUNE_CACHE") or None
+    if args.tune:
+        tune = json.loads(args.tune)
+    else:
+        tune, _ = autotune.tune_plan(shape, obj, probe, pos, I_meas, grads=grads, cache_path=cache,
+                                     use_cache=cache is not None)
+    plan = Plan.for_problem(start, tune=tune)
     out = plan.forward_adjoint(obj, probe, pos, I_meas, grads=grads)
 
     def step(plain=False):
@@ -219,12 +234,13 @@ def main():
                    "form": "fused persistent kernel"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "fused_small_kernel<128,512,1>",
+                     "traffic": traffic, "kernel": "fused_small_kernel<128,%d,1>" % plan.info()["threads"],
                      "kernel_ms": k_avg_ms, "flops_per_pattern": flops_pp},
         "hbm": {"alg_bytes_per_pattern": bytes_pp, "alg_GBs": hbm_alg_gbs, "frac_of_peak": hbm_alg_gbs / HBM_PEAK_GBS},
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
         "cpu_baseline": cpu,
+        "tune": tune,
         "error_flags": flags,
         "kernel_hash": khash,
     }
