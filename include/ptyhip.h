@@ -94,7 +94,9 @@ typedef struct {
 
 /* Optional implementation choices (the autotuner's search space). Zero = default. */
 typedef struct {
-  int32_t variant;      /* fused on-chip kernel thread layout: 0 = 512 threads, 1 = alternative */
+  int32_t variant;      /* on-chip fused kernel (64^2, 128^2): 0 = 512 threads, patch in scratch;
+                           1 = 1024 (128^2) / 256 (64^2) threads; 2 = 512 threads, patch and
+                           patch gradient in registers; 3 = as 2 with 1024 / 256 threads */
   int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
   int32_t recompute;    /* 1 = recompute (multislice: incident waves; several modes: far fields)
                            instead of keeping them in workgroup scratch */

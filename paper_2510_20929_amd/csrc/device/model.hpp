@@ -36,28 +36,22 @@ __device__ __forceinline__ PosInfo parse_position(const float* __restrict__ pos,
   return p;
 }
 
-// Bilinear sample of a slice at window pixel (y, x); zero-weight taps are not read.
+// Bilinear sample of a slice at window pixel (y, x). A tap whose weight is zero (an
+// integer coordinate) re-reads the base pixel instead of the next one, so the reads
+// stay inside the N x N window and the code has no per-pixel branches.
 __device__ __forceinline__ float2 bilinear(const float2* __restrict__ O, int W, const PosInfo& p, int y, int x) {
   const float2* r0 = O + size_t(p.y0 + y) * W + (p.x0 + x);
+  const int dx = p.fx > 0.f ? 1 : 0;
+  const int dy = p.fy > 0.f ? W : 0;
   const float wy0 = 1.f - p.fy, wx0 = 1.f - p.fx;
-  float2 a = r0[0];
+  const float2 a = r0[0], b = r0[dx], c = r0[dy], d = r0[dy + dx];
   float2 v = cscale(a, wy0 * wx0);
-  if (p.fx > 0.f) {
-    float2 b = r0[1];
-    v.x = fmaf(wy0 * p.fx, b.x, v.x);
-    v.y = fmaf(wy0 * p.fx, b.y, v.y);
-  }
-  if (p.fy > 0.f) {
-    const float2* r1 = r0 + W;
-    float2 c = r1[0];
-    v.x = fmaf(p.fy * wx0, c.x, v.x);
-    v.y = fmaf(p.fy * wx0, c.y, v.y);
-    if (p.fx > 0.f) {
-      float2 d = r1[1];
-      v.x = fmaf(p.fy * p.fx, d.x, v.x);
-      v.y = fmaf(p.fy * p.fx, d.y, v.y);
-    }
-  }
+  v.x = fmaf(wy0 * p.fx, b.x, v.x);
+  v.y = fmaf(wy0 * p.fx, b.y, v.y);
+  v.x = fmaf(p.fy * wx0, c.x, v.x);
+  v.y = fmaf(p.fy * wx0, c.y, v.y);
+  v.x = fmaf(p.fy * p.fx, d.x, v.x);
+  v.y = fmaf(p.fy * p.fx, d.y, v.y);
   return v;
 }
 

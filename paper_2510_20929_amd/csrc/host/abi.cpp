@@ -114,7 +114,7 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   const int recompute = p->tune.recompute ? 1 : 0;
   if (p->on_chip) {
     p->threads = fused_small_threads(N, p->tune.variant);
-    p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off);
+    p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off, p->tune.variant);
   } else {
     p->threads = 256;
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
@@ -393,7 +393,7 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0 || tune->plain_chunk < 0 ||
+  if (tune && (tune->variant < 0 || tune->variant > 3 || tune->grid < 0 || tune->plain_chunk < 0 ||
                tune->recompute < 0))
     return PTYHIP_EINVAL;
   Plan* p = new (std::nothrow) Plan();

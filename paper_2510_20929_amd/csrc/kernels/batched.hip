@@ -43,7 +43,7 @@ __global__ __launch_bounds__(BT) void batched_kernel(const BatchEntry* __restric
 }
 
 size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off) {
-  if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, 0, pacc_off);
+  if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, 0, pacc_off, 0);
   return big_scratch_elems(N, M, E, pacc_off);
 }
 

@@ -5,10 +5,10 @@
 
 namespace ptyhip {
 
-template <int N, int T, int LOSS>
+template <int N, int T, int LOSS, bool RV>
 __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   __shared__ SmallShared<N, T> sh;
-  small_body<N, T, LOSS>(a, sh, blockIdx.x, gridDim.x);
+  small_body<N, T, LOSS, RV>(a, sh, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------- multislice
@@ -221,15 +221,15 @@ __global__ void probe_reduce_kernel(const float2* __restrict__ scratch, size_t s
 }
 
 // ----------------------------------------------------------------------------- launchers
-template <int N, int T>
+template <int N, int T, bool RV = false>
 static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   const bool ms = a.S > 1;
   if (a.loss == 0) {
     if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV>), dim3(grid), dim3(T), 0, st, a);
   } else {
     if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1, RV>), dim3(grid), dim3(T), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -244,22 +244,26 @@ static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, i
   return hipGetLastError();
 }
 
+// variants: 0 = 512 threads, scratch-resident patch; 1 = 1024 (128^2) or 256 (64^2)
+// threads, scratch-resident patch; 2 = 512 threads, register-resident patch;
+// 3 = 1024 (128^2) or 256 (64^2) threads, register-resident patch
 int fused_small_threads(int N, int variant) {
   switch (N) {
     case 16: return 64;
     case 32: return 128;
-    case 64: return variant == 1 ? 256 : 512;
-    case 128: return variant == 1 ? 1024 : 512;
+    case 64: return (variant == 1 || variant == 3) ? 256 : 512;
+    case 128: return (variant == 1 || variant == 3) ? 1024 : 512;
     default: return 0;
   }
 }
 
 // per-workgroup scratch (float2 elements) and the offset of the probe accumulator
-size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off) {
+size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant) {
   const size_t fr = size_t(N) * N;
   size_t base;
-  if (S <= 1) base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
-  else base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
+  else base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
   *pacc_off = base;
   return base + fr * size_t(E) * M;
 }
@@ -268,8 +272,16 @@ hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, h
   switch (N) {
     case 16: return launch_small_t<16, 64>(a, grid, st);
     case 32: return launch_small_t<32, 128>(a, grid, st);
-    case 64: return variant == 1 ? launch_small_t<64, 256>(a, grid, st) : launch_small_t<64, 512>(a, grid, st);
-    case 128: return variant == 1 ? launch_small_t<128, 1024>(a, grid, st) : launch_small_t<128, 512>(a, grid, st);
+    case 64:
+      if (variant == 1) return launch_small_t<64, 256>(a, grid, st);
+      if (variant == 3) return launch_small_t<64, 256, true>(a, grid, st);
+      if (variant == 2) return launch_small_t<64, 512, true>(a, grid, st);
+      return launch_small_t<64, 512>(a, grid, st);
+    case 128:
+      if (variant == 1) return launch_small_t<128, 1024>(a, grid, st);
+      if (variant == 3) return launch_small_t<128, 1024, true>(a, grid, st);
+      if (variant == 2) return launch_small_t<128, 512, true>(a, grid, st);
+      return launch_small_t<128, 512>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -280,11 +292,12 @@ hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int 
     case 16: return probe_reduce_t<16, 64>(a, grid, g_probe, accumulate, st);
     case 32: return probe_reduce_t<32, 128>(a, grid, g_probe, accumulate, st);
     case 64:
-      return variant == 1 ? probe_reduce_t<64, 256>(a, grid, g_probe, accumulate, st)
-                          : probe_reduce_t<64, 512>(a, grid, g_probe, accumulate, st);
+      return fused_small_threads(64, variant) == 256 ? probe_reduce_t<64, 256>(a, grid, g_probe, accumulate, st)
+                                                     : probe_reduce_t<64, 512>(a, grid, g_probe, accumulate, st);
     case 128:
-      return variant == 1 ? probe_reduce_t<128, 1024>(a, grid, g_probe, accumulate, st)
-                          : probe_reduce_t<128, 512>(a, grid, g_probe, accumulate, st);
+      return fused_small_threads(128, variant) == 1024
+                 ? probe_reduce_t<128, 1024>(a, grid, g_probe, accumulate, st)
+                 : probe_reduce_t<128, 512>(a, grid, g_probe, accumulate, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -20,6 +20,8 @@
 // Multislice: incident waves and patches of every slice live in the workgroup
 // scratch (L2/MALL resident), or the incident waves are recomputed.
 #pragma once
+#include <type_traits>
+
 #include "../device/fft.hpp"
 #include "../device/model.hpp"
 #include "args.hpp"
@@ -50,6 +52,27 @@ struct SmallCtx {
   }
 };
 
+// Calls f(i, P) for the thread's elements i (layout A) with P = the probe of mode m at
+// the current position. The three cases (no weights, one weighted eigenprobe, a
+// weighted sum of eigenprobes) are separate straight-line loops so that the loads of
+// all elements are in flight together.
+template <int N, int T, class Fn>
+__device__ __forceinline__ void for_probe(const CallArgs& a, const float* wk, int m, int t, Fn&& f) {
+  using C = SmallCtx<N, T>;
+  const float2* __restrict__ U0 = a.probe + size_t(m) * C::NN;
+  if (wk == nullptr) {
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) f(i, U0[C::a_pix(t, i)]);
+  } else if (a.E == 1) {
+    const float w = wk[0];
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) f(i, cscale(U0[C::a_pix(t, i)], w));
+  } else {
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) f(i, probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)));
+  }
+}
+
 // Zero every per-position output of an invalid position and latch the error.
 template <int N, int T>
 __device__ __forceinline__ void skip_position(const CallArgs& a, int k, const PosInfo& p) {
@@ -79,13 +102,19 @@ __device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&
   using C = SmallCtx<N, T>;
   const float* im = a.imeas + size_t(k) * C::NN;
   const int t = opaque_tid();
+  float imv[C::E];
+#pragma unroll
+  for (int i = 0; i < C::E; ++i) imv[i] = __builtin_nontemporal_load(im + C::d_centred(t, i));
+  if (a.ipred) {
+    float* ip = a.ipred + size_t(k) * C::NN;
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) __builtin_nontemporal_store(Iacc[i], ip + C::d_centred(t, i));
+  }
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < C::E; ++i) {
-    const int ci = C::d_centred(t, i);
     float l, c;
-    loss_terms<LOSS>(Iacc[i], im[ci], a.eps, l, c);
-    if (a.ipred) a.ipred[size_t(k) * C::NN + ci] = Iacc[i];
+    loss_terms<LOSS>(Iacc[i], imv[i], a.eps, l, c);
     lsum += double(l);
     Iacc[i] = c;
   }
@@ -162,29 +191,43 @@ __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p,
   const bool want_obj = (a.want & WANT_OBJ) && gwin != nullptr;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
   const float2 z = make_float2(0.f, 0.f);
-  for (int idx = threadIdx.x; idx < WN * WN; idx += T) {
-    const int py = idx / WN, px = idx - py * WN;
-    const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
-    const float2 g00 = (iy0 && ix0) ? lds[py * P + px] : z;
-    const float2 g01 = (iy0 && ix1) ? lds[py * P + px - 1] : z;
-    const float2 g10 = (iy1 && ix0) ? lds[(py - 1) * P + px] : z;
-    const float2 g11 = (iy1 && ix1) ? lds[(py - 1) * P + px - 1] : z;
-    if (want_obj) {
-      float2 g;
-      g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
-      g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
-      gwin[idx] = g;
+  auto body = [&](auto obj_c, auto pos_c) {
+    constexpr bool OBJ = decltype(obj_c)::value, POS = decltype(pos_c)::value;
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < WN * WN; idx += T) {
+      const int py = idx / WN, px = idx - py * WN;
+      const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
+      const float2 g00 = (iy0 && ix0) ? lds[py * P + px] : z;
+      const float2 g01 = (iy0 && ix1) ? lds[py * P + px - 1] : z;
+      const float2 g10 = (iy1 && ix0) ? lds[(py - 1) * P + px] : z;
+      const float2 g11 = (iy1 && ix1) ? lds[(py - 1) * P + px - 1] : z;
+      if constexpr (OBJ) {
+        float2 g;
+        g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
+        g.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
+        float* gw = reinterpret_cast<float*>(gwin + idx);
+        __builtin_nontemporal_store(g.x, gw);
+        __builtin_nontemporal_store(g.y, gw + 1);
+      }
+      if constexpr (POS) {
+        const float2 A = Os[size_t(p.y0 + py) * a.W + (p.x0 + px)];
+        float2 hy, hx;
+        hy.x = (1.f - p.fx) * (g10.x - g00.x) + p.fx * (g11.x - g01.x);
+        hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
+        hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
+        hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
+        gy += double(cdotre(hy, A));
+        gx += double(cdotre(hx, A));
+      }
     }
-    if (want_pos) {
-      const float2 A = Os[size_t(p.y0 + py) * a.W + (p.x0 + px)];
-      float2 hy, hx;
-      hy.x = (1.f - p.fx) * (g10.x - g00.x) + p.fx * (g11.x - g01.x);
-      hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
-      hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
-      hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
-      gy += double(cdotre(hy, A));
-      gx += double(cdotre(hx, A));
-    }
+  };
+  using T0 = std::false_type;
+  using T1 = std::true_type;
+  if (want_obj) {
+    if (want_pos) body(T1{}, T1{});
+    else body(T1{}, T0{});
+  } else if (want_pos) {
+    body(T0{}, T1{});
   }
 }
 
@@ -207,10 +250,6 @@ __device__ __forceinline__ void finish_position(const CallArgs& a, int k, double
 }
 
 // ----------------------------------------------------------------------------- single slice
-// Registers hold only the working frame v and dl/dI (3 E floats per thread). The
-// workgroup's scratch ([E][T] frames, coalesced) holds the patch o, the running patch
-// gradient sum_m conj(P_m) g_m (several modes), the far fields of all but the last
-// mode (unless they are recomputed), and the probe-gradient accumulator.
 // LDS the body needs (the caller owns it so that one kernel can host several bodies)
 template <int N, int T>
 struct SmallShared {
@@ -222,7 +261,14 @@ struct SmallShared {
 };
 
 // Workgroup `wg` of `nwg` processes positions wg, wg + nwg, ... of the call `a`.
-template <int N, int T, int LOSS>
+//
+// RV = false: registers hold only the working frame v and dl/dI (3 E floats per
+// thread); the patch o and the running patch gradient sum_m conj(P_m) g_m live in
+// the workgroup's scratch frames.
+// RV = true (512 threads): o and the running patch gradient stay in registers and only
+// dl/dI (fp32) is parked in scratch between its uses, which removes most of the
+// scratch traffic at the price of about twice the registers.
+template <int N, int T, int LOSS, bool RV = false>
 __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>& sh, int wg, int nwg) {
   using F = Frame2D<N, T>;
   using C = SmallCtx<N, T>;
@@ -237,12 +283,15 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
   const bool adj = a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH;
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
   for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
-  // scratch: patch [NN], patch-gradient accumulator [NN], far fields of modes 0..M-2,
-  // probe-gradient accumulator [E][M][NN]
-  float2* obuf = a.scratch + size_t(wg) * a.scratch_stride;
-  float2* gacc = obuf + size_t(C::NN);
-  float2* psis = gacc + size_t(C::NN);
-  float2* pacc = obuf + a.pacc_off;
+  // scratch (RV = false): patch [NN], patch-gradient accumulator [NN], far fields of
+  //   modes 0..M-2 [M-1][NN] (unless recomputed), probe accumulator [E][M][NN]
+  // scratch (RV = true): dl/dI [NN floats], far fields [M-1][NN], probe accumulator
+  float2* scr = a.scratch + size_t(wg) * a.scratch_stride;
+  float2* obuf = scr;
+  float2* gacc = scr + size_t(C::NN);
+  float2* psis = RV ? scr + size_t(C::NN) / 2 : gacc + size_t(C::NN);
+  float* cbuf = reinterpret_cast<float*>(scr);
+  float2* pacc = scr + a.pacc_off;
   if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
 
   for (int k = wg; k < a.K; k += nwg) {
@@ -257,14 +306,22 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
 
+    float2 o[RV ? E : 1];
     {
       const int t = opaque_tid();
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         const int l = i / C::N2, j = i % C::N2;
-        obuf[size_t(i) * T + t] = bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
+        const float2 val = bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
+        if constexpr (RV) o[i] = val;
+        else obuf[size_t(i) * T + t] = val;
       }
     }
+    // patch value of element i (thread t)
+    auto patch = [&](int i, int t) -> float2 {
+      if constexpr (RV) return o[i];
+      else return obuf[size_t(i) * T + t];
+    };
 
     float2 v[E];
     float cf[E];
@@ -274,9 +331,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
       for (int m = 0; m < a.M; ++m) {
         {
           const int t = opaque_tid();
-#pragma unroll
-          for (int i = 0; i < E; ++i)
-            v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+          for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) { v[i] = cmul(P, patch(i, t)); });
         }
         F::forward(v, lds, tws, inv_n);
 #pragma unroll
@@ -298,9 +353,15 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
       if (a.mode == MODE_APPLY_A) continue;
       if (!position_loss<N, T, LOSS>(a, k, cf, red)) continue;
       if (a.mode == MODE_FORWARD) continue;
+      if constexpr (RV) {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) cbuf[size_t(i) * T + t] = cf[i];
+      }
     }
 
     // adjoint, last mode first (its far field is still in registers)
+    float2 go[RV ? E : 1];
     for (int mm = 0; mm < a.M; ++mm) {
       const int m = a.M - 1 - mm;
       if (!fwd) {
@@ -313,9 +374,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
           const int t = opaque_tid();
           if (a.recompute) {
             // recompute this mode's far field instead of reading it back
-#pragma unroll
-            for (int i = 0; i < E; ++i)
-              v[i] = cmul(probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)), obuf[size_t(i) * T + t]);
+            for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) { v[i] = cmul(P, patch(i, t)); });
             F::forward(v, lds, tws, inv_n);
           } else {
             const float2* ps = psis + size_t(m) * C::NN;
@@ -323,23 +382,47 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
             for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
           }
         }
+        const int t = opaque_tid();
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
+        for (int i = 0; i < E; ++i) {
+          if constexpr (RV) v[i] = cscale(v[i], a.gscale * cbuf[size_t(i) * T + t]);
+          else v[i] = cscale(v[i], a.gscale * cf[i]);
+        }
       }
       F::inverse(v, lds, tws, inv_n);
       const bool last = mm == a.M - 1;
       __syncthreads();  // every thread is done reading LDS before the patch gradient lands there
       {
         const int t = opaque_tid();
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-          const int pix = C::a_pix(t, i);
-          float2 go = cmulc(probe_at(a.probe, wk, a.E, a.M, C::NN, m, pix), v[i]);
-          const size_t si = size_t(i) * T + t;
-          if (mm > 0) go = cadd(go, gacc[si]);
-          if (last) lds[(pix / N) * F::P + (pix % N)] = go;
-          else gacc[si] = go;
-          v[i] = cmulc(obuf[si], v[i]);
+        // patch gradient += conj(P_m) g_m (first / last mode as separate straight-line
+        // loops), then v = conj(o) g_m for the probe gradient
+        auto pass = [&](auto first_c, auto last_c) {
+          constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
+          for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) {
+            float2 g = cmulc(P, v[i]);
+            const size_t si = size_t(i) * T + t;
+            if constexpr (RV) {
+              if constexpr (!FIRST) g = cadd(g, go[i]);
+              go[i] = g;
+            } else {
+              if constexpr (!FIRST) g = cadd(g, gacc[si]);
+              if constexpr (!LAST) gacc[si] = g;
+            }
+            if constexpr (LAST) {
+              const int pix = C::a_pix(t, i);
+              lds[(pix / N) * F::P + (pix % N)] = g;
+            }
+            v[i] = cmulc(patch(i, t), v[i]);
+          });
+        };
+        using T0 = std::false_type;
+        using T1 = std::true_type;
+        if (mm == 0) {
+          if (last) pass(T1{}, T1{});
+          else pass(T1{}, T0{});
+        } else {
+          if (last) pass(T0{}, T1{});
+          else pass(T0{}, T0{});
         }
       }
       probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);

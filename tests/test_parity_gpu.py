@@ -85,3 +85,18 @@ def test_frame512(plain):
     ref = run_oracle(start, I, grads)
     got = run_gpu(_plan(start), start, I, grads, plain=plain)
     compare(got, ref, grads, tag=f"N=512 {'plain' if plain else 'fused'}")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("recompute", [0, 1])
+@pytest.mark.parametrize("N", [64, 128])
+def test_fused_variants(N, variant, recompute):
+    """Every thread layout of the on-chip fused kernel (scratch- or register-resident
+    patch), storing or recomputing the far fields, against the oracle."""
+    start, I = custom_problem(300 + N + 10 * variant + recompute, N, 3, 2, 1, N * 3, 90, loss="poisson",
+                              weights="opr")
+    grads = ("obj", "probe", "pos", "weights")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute}), start, I, grads)
+    compare(got, ref, grads, tag=f"N={N} variant={variant} recompute={recompute}")
+    assert got["flags"] == 0
