@@ -18,12 +18,31 @@ __global__ __launch_bounds__(BIG_T) void fused_big_kernel(CallArgs a) {
   big_body<N, BIG_T, LOSS>(a, sh, blockIdx.x, gridDim.x);
 }
 
-__global__ void probe_reduce_big_kernel(const float2* __restrict__ scratch, size_t stride, size_t pacc_off,
-                                        int groups, size_t n, float2* g_probe, int accumulate) {
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += size_t(gridDim.x) * blockDim.x) {
+__global__ __launch_bounds__(256) void probe_reduce_big_kernel(const float2* __restrict__ scratch, size_t stride,
+                                                               size_t pacc_off, int groups, size_t n,
+                                                               float2* g_probe, int accumulate) {
+  // 64 elements per block; four waves sum interleaved quarters of the workgroup copies
+  // (8 loads in flight each) and combine them in a fixed order
+  __shared__ float2 part[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const size_t g = size_t(blockIdx.x) * 64 + lane;
+  float2 s = make_float2(0.f, 0.f);
+  if (g < n) {
     const float2* src = scratch + pacc_off + g;
-    float2 s = make_float2(0.f, 0.f);
-    for (int w = 0; w < groups; ++w) s = cadd(s, src[size_t(w) * stride]);
+    int w = q;
+    for (; w + 28 < groups; w += 32) {
+      float2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[size_t(w + 4 * u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = cadd(s, v[u]);
+    }
+    for (; w < groups; w += 4) s = cadd(s, src[size_t(w) * stride]);
+  }
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && g < n) {
+    s = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
     g_probe[g] = accumulate ? cadd(g_probe[g], s) : s;
   }
 }
@@ -47,8 +66,7 @@ hipError_t launch_fused_big(const CallArgs& a, int N, int grid, hipStream_t st) 
 hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g_probe, int accumulate,
                                    hipStream_t st) {
   const size_t n = size_t(a.E) * a.M * N * N;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  const size_t blocks = (n + 63) / 64;
   hipLaunchKernelGGL(probe_reduce_big_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, a.scratch, a.scratch_stride,
                      a.pacc_off, grid, n, g_probe, accumulate);
   return hipGetLastError();

@@ -205,16 +205,35 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
 // g_probe[e][m][pix] (+)= sum over workgroups of their accumulator frames, mapping the
 // scratch element i*T + t back to pixel a_pix(t, i).
 template <int N, int T>
-__global__ void probe_reduce_kernel(const float2* __restrict__ scratch, size_t stride, size_t pacc_off, int groups,
-                                    int EM, float2* g_probe, int accumulate) {
+__global__ __launch_bounds__(256) void probe_reduce_kernel(const float2* __restrict__ scratch, size_t stride,
+                                                           size_t pacc_off, int groups, int EM, float2* g_probe,
+                                                           int accumulate) {
+  // 64 accumulator elements per block; the four waves sum interleaved quarters of the
+  // workgroup copies (8 loads in flight each), then combine in a fixed order
   using C = SmallCtx<N, T>;
+  __shared__ float2 part[4][64];
   const size_t n = size_t(EM) * C::NN;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += size_t(gridDim.x) * blockDim.x) {
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const size_t g = size_t(blockIdx.x) * 64 + lane;
+  float2 s = make_float2(0.f, 0.f);
+  if (g < n) {
+    const float2* src = scratch + pacc_off + g;
+    int w = q;
+    for (; w + 28 < groups; w += 32) {
+      float2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[size_t(w + 4 * u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = cadd(s, v[u]);
+    }
+    for (; w < groups; w += 4) s = cadd(s, src[size_t(w) * stride]);
+  }
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && g < n) {
+    s = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
     const size_t em = g / C::NN, r = g % C::NN;
     const int i = int(r / T), t = int(r % T);
-    const float2* src = scratch + pacc_off + em * C::NN + r;
-    float2 s = make_float2(0.f, 0.f);
-    for (int w = 0; w < groups; ++w) s = cadd(s, src[size_t(w) * stride]);
     float2* dst = g_probe + em * C::NN + C::a_pix(t, i);
     *dst = accumulate ? cadd(*dst, s) : s;
   }
@@ -237,8 +256,7 @@ static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
 template <int N, int T>
 static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, int accumulate, hipStream_t st) {
   const size_t n = size_t(a.E) * a.M * N * N;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  const size_t blocks = (n + 63) / 64;
   hipLaunchKernelGGL((probe_reduce_kernel<N, T>), dim3(unsigned(blocks)), dim3(256), 0, st, a.scratch,
                      a.scratch_stride, a.pacc_off, grid, a.E * a.M, g_probe, accumulate);
   return hipGetLastError();
