@@ -35,6 +35,34 @@ __device__ __forceinline__ float2 mul_mi(float2 a) {
   else return make_float2(a.y, -a.x);
 }
 
+// ----------------------------------------------------------------------------- buffer-resource frames
+// A workgroup-private frame of complex values addressed through a buffer resource:
+// element (i, t) of a [E][T] layout is at byte t*8 (one VGPR per thread) plus i*T*8 (a
+// scalar offset), so unrolled loops over i need no per-element 64-bit addresses.
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+
+struct BufFrame {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ BufFrame(const void* base, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), BUF_RSRC_WORD3)) {}
+  __device__ __forceinline__ float2 ld(int voff, int soff) const {
+    const f2v_t v = __builtin_bit_cast(f2v_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return make_float2(v.x, v.y);
+  }
+  __device__ __forceinline__ void st(float2 x, int voff, int soff) const {
+    const f2v_t v = {x.x, x.y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                          r, voff, soff, 0);
+  }
+  __device__ __forceinline__ float ldf(int voff, int soff) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ void stf(float x, int voff, int soff) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, voff, soff, 0);
+  }
+};
+
 // ----------------------------------------------------------------------------- optimisation barriers
 // An empty asm statement that makes a value opaque to the optimiser, so that values
 // derived from it inside a loop body are recomputed there instead of being hoisted

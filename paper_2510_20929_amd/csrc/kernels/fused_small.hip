@@ -39,6 +39,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   float2* Gp = Op + size_t(S) * FR;                   // [S][FR]
   float2* Ps = Gp + size_t(S) * FR;                   // [M][S][FR]
   float2* pacc = scr + a.pacc_off;
+  const BufFrame sbf(scr, uint32_t(a.scratch_stride * sizeof(float2)));
   const size_t HW = size_t(a.H) * a.W;
   if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
 
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
           F::inverse(v, lds, tws, inv_n);
         }
       }
-      probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);
+      probe_gradients<N, T>(a, m, wk, v, sbf, int(a.pacc_off * sizeof(float2)), red, wacc);
     }
 
     double gy = 0.0, gx = 0.0;

@@ -56,20 +56,36 @@ struct SmallCtx {
 // the current position. The three cases (no weights, one weighted eigenprobe, a
 // weighted sum of eigenprobes) are separate straight-line loops so that the loads of
 // all elements are in flight together.
-template <int N, int T, class Fn>
+// CH > 0 limits how many elements' loads the scheduler may hoist ahead of their use
+// (a scheduling barrier every CH elements), for register-tight callers.
+template <int N, int T, int CH = 0, class Fn>
 __device__ __forceinline__ void for_probe(const CallArgs& a, const float* wk, int m, int t, Fn&& f) {
   using C = SmallCtx<N, T>;
   const float2* __restrict__ U0 = a.probe + size_t(m) * C::NN;
+  auto fence = [](int i) {
+    if constexpr (CH > 0) {
+      if ((i + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   if (wk == nullptr) {
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) f(i, U0[C::a_pix(t, i)]);
+    for (int i = 0; i < C::E; ++i) {
+      f(i, U0[C::a_pix(t, i)]);
+      fence(i);
+    }
   } else if (a.E == 1) {
     const float w = wk[0];
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) f(i, cscale(U0[C::a_pix(t, i)], w));
+    for (int i = 0; i < C::E; ++i) {
+      f(i, cscale(U0[C::a_pix(t, i)], w));
+      fence(i);
+    }
   } else {
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) f(i, probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)));
+    for (int i = 0; i < C::E; ++i) {
+      f(i, probe_at(a.probe, wk, a.E, a.M, C::NN, m, C::a_pix(t, i)));
+      fence(i);
+    }
   }
 }
 
@@ -143,26 +159,33 @@ __device__ __forceinline__ void zero_probe_acc(const CallArgs& a, float2* acc) {
 }
 
 // Probe-side gradients of one mode from the gradient gP of the incident probe wave
-// (layout A): accumulate w_e gP into the workgroup's accumulator frames, and the
-// OPR weight-gradient sums Re<gP, U_e,m>.
-template <int N, int T>
+// (layout A): accumulate w_e gP into the workgroup's accumulator frames ([E][M] frames
+// starting at byte offset acc_b of the scratch buffer `sb`), and the OPR weight-gradient
+// sums Re<gP, U_e,m>.
+// The accumulator is read CH elements at a time (all loads of a chunk in flight).
+template <int N, int T, int CH = Frame2D<N, T>::E>
 __device__ __forceinline__ void probe_gradients(const CallArgs& a, int m, const float* wk,
-                                                const float2 (&gP)[Frame2D<N, T>::E], float2* acc, double* red,
-                                                double* wacc) {
+                                                const float2 (&gP)[Frame2D<N, T>::E], const BufFrame& sb, int acc_b,
+                                                double* red, double* wacc) {
   using C = SmallCtx<N, T>;
+  static_assert(C::E % CH == 0, "chunk must divide the elements per thread");
   const int t = opaque_tid();
-  if ((a.want & WANT_PROBE) && acc) {
+  if (a.want & WANT_PROBE) {
     const int ne = wk ? a.E : 1;
     for (int e = 0; e < ne; ++e) {
-      float2* fr = acc + (size_t(e) * a.M + m) * C::NN;
+      const int fb = acc_b + (e * a.M + m) * C::NN * 8;
       const float w = wk ? wk[e] : 1.f;
 #pragma unroll
-      for (int i = 0; i < C::E; ++i) {
-        const size_t si = size_t(i) * T + t;
-        float2 g = fr[si];
-        g.x = fmaf(w, gP[i].x, g.x);
-        g.y = fmaf(w, gP[i].y, g.y);
-        fr[si] = g;
+      for (int i0 = 0; i0 < C::E; i0 += CH) {
+        float2 g[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) g[u] = sb.ld(t * 8, fb + (i0 + u) * T * 8);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          g[u].x = fmaf(w, gP[i0 + u].x, g[u].x);
+          g[u].y = fmaf(w, gP[i0 + u].y, g[u].y);
+          sb.st(g[u], t * 8, fb + (i0 + u) * T * 8);
+        }
       }
     }
   }
@@ -286,13 +309,15 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
   // scratch (RV = false): patch [NN], patch-gradient accumulator [NN], far fields of
   //   modes 0..M-2 [M-1][NN] (unless recomputed), probe accumulator [E][M][NN]
   // scratch (RV = true): dl/dI [NN floats], far fields [M-1][NN], probe accumulator
+  // byte offsets inside the workgroup's scratch: patch at 0, patch-gradient accumulator
+  // at NN, far fields after them (RV: dl/dI floats at 0, far fields at NN/2), probe
+  // accumulator at pacc_off
   float2* scr = a.scratch + size_t(wg) * a.scratch_stride;
-  float2* obuf = scr;
-  float2* gacc = scr + size_t(C::NN);
-  float2* psis = RV ? scr + size_t(C::NN) / 2 : gacc + size_t(C::NN);
-  float* cbuf = reinterpret_cast<float*>(scr);
-  float2* pacc = scr + a.pacc_off;
-  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
+  const BufFrame sb(scr, uint32_t(a.scratch_stride * sizeof(float2)));
+  constexpr int GACC_B = C::NN * 8;
+  constexpr int PSIS_B = (RV ? C::NN / 2 : 2 * C::NN) * 8;
+  const int pacc_b = int(a.pacc_off * sizeof(float2));
+  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
 
   for (int k = wg; k < a.K; k += nwg) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -314,13 +339,13 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
         const int l = i / C::N2, j = i % C::N2;
         const float2 val = bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j));
         if constexpr (RV) o[i] = val;
-        else obuf[size_t(i) * T + t] = val;
+        else sb.st(val, t * 8, i * T * 8);
       }
     }
     // patch value of element i (thread t)
     auto patch = [&](int i, int t) -> float2 {
       if constexpr (RV) return o[i];
-      else return obuf[size_t(i) * T + t];
+      else return sb.ld(t * 8, i * T * 8);
     };
 
     float2 v[E];
@@ -339,9 +364,9 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
         if (m < a.M - 1 && a.mode == MODE_FWD_ADJ && !a.recompute) {
           // keep this mode's far field for the adjoint (the last one stays in registers)
           const int t = opaque_tid();
-          float2* ps = psis + size_t(m) * C::NN;
+          const int pb = PSIS_B + m * C::NN * 8;
 #pragma unroll
-          for (int i = 0; i < E; ++i) ps[size_t(i) * T + t] = v[i];
+          for (int i = 0; i < E; ++i) sb.st(v[i], t * 8, pb + i * T * 8);
         }
         if (a.mode == MODE_APPLY_A) {
           const int t = opaque_tid();
@@ -356,12 +381,14 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
       if constexpr (RV) {
         const int t = opaque_tid();
 #pragma unroll
-        for (int i = 0; i < E; ++i) cbuf[size_t(i) * T + t] = cf[i];
+        for (int i = 0; i < E; ++i) sb.stf(cf[i], t * 4, i * T * 4);
       }
     }
 
     // adjoint, last mode first (its far field is still in registers)
     float2 go[RV ? E : 1];
+#pragma unroll
+    for (int i = 0; i < (RV ? E : 1); ++i) go[i] = make_float2(0.f, 0.f);
     for (int mm = 0; mm < a.M; ++mm) {
       const int m = a.M - 1 - mm;
       if (!fwd) {
@@ -377,15 +404,15 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
             for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) { v[i] = cmul(P, patch(i, t)); });
             F::forward(v, lds, tws, inv_n);
           } else {
-            const float2* ps = psis + size_t(m) * C::NN;
+            const int pb = PSIS_B + m * C::NN * 8;
 #pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = ps[size_t(i) * T + t];
+            for (int i = 0; i < E; ++i) v[i] = sb.ld(t * 8, pb + i * T * 8);
           }
         }
         const int t = opaque_tid();
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-          if constexpr (RV) v[i] = cscale(v[i], a.gscale * cbuf[size_t(i) * T + t]);
+          if constexpr (RV) v[i] = cscale(v[i], a.gscale * sb.ldf(t * 4, i * T * 4));
           else v[i] = cscale(v[i], a.gscale * cf[i]);
         }
       }
@@ -398,15 +425,14 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
         // loops), then v = conj(o) g_m for the probe gradient
         auto pass = [&](auto first_c, auto last_c) {
           constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
-          for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) {
+          for_probe<N, T, (RV ? 4 : 0)>(a, wk, m, t, [&](int i, float2 P) {
             float2 g = cmulc(P, v[i]);
-            const size_t si = size_t(i) * T + t;
             if constexpr (RV) {
               if constexpr (!FIRST) g = cadd(g, go[i]);
               go[i] = g;
             } else {
-              if constexpr (!FIRST) g = cadd(g, gacc[si]);
-              if constexpr (!LAST) gacc[si] = g;
+              if constexpr (!FIRST) g = cadd(g, sb.ld(t * 8, GACC_B + i * T * 8));
+              if constexpr (!LAST) sb.st(g, t * 8, GACC_B + i * T * 8);
             }
             if constexpr (LAST) {
               const int pix = C::a_pix(t, i);
@@ -425,7 +451,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
           else pass(T0{}, T0{});
         }
       }
-      probe_gradients<N, T>(a, m, wk, v, pacc, red, wacc);
+      probe_gradients<N, T, (RV ? 4 : E)>(a, m, wk, v, sb, pacc_b, red, wacc);
     }
 
     __syncthreads();
