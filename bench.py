@@ -8,6 +8,11 @@ positions. One step = one forward + adjoint pass over all 2000 patterns with inp
 resident in HBM. The fused kernel is timed; the per-step form is timed beside it.
 
 Prints one JSON line. `value` is patterns/s of the fused form.
+
+`--workload` measures one of the other synthetic workloads the same way (one JSON line
+each): c1m0 (config 1 with mode 0 only), c0, c2, c3, c5 (30 probe modes, the paper's
+benchmark shape) and c4 (32 uneven datasets in one batched, graph-captured launch).
+The default (config 1) is the headline measurement.
 """
 from __future__ import annotations
 
@@ -60,16 +65,16 @@ def algorithmic(prob):
     return flops, byts
 
 
-def read_traffic(khash: str):
+def read_traffic(khash: str, kernel: str):
     """HBM bytes per launch of the fused kernel from the committed PMC summary, if it
-    was taken on the current kernel sources."""
+    was taken on the current kernel sources and the same kernel instance."""
     path = os.path.join(ROOT, "profiles", "fused_c1_traffic.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != khash:
+    if t.get("kernel_hash") != khash or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
@@ -104,12 +109,112 @@ def cpu_baseline(truth, start, budget_s: float = 12.0):
                       f"chunks of 25), FP64 NumPy oracle, {dt:.1f} s, one thread"}
 
 
+WORKLOADS = {
+    "c1": "config 1: 1024x1024 complex object, 4 Hermite-Gauss probe modes of 128x128, 2000 Fermat-spiral "
+          "positions with sub-pixel offsets, Poisson loss, gradients of object, probe and positions",
+    "c1m0": "config 1 with probe mode 0 only (M = 1): 1024x1024 object, 128x128 frames, 2000 positions, "
+            "Poisson loss, gradients of object, probe and positions",
+    "c0": "config 0: 256x256 object, one 64x64 disk probe, 625 integer raster positions, amplitude loss, "
+          "gradients of object and probe",
+    "c2": "config 2: 2048x2048 object, 8 orthogonal eigenprobes of 256x256 with per-position weights, "
+          "10000 jittered raster positions, amplitude loss, gradients of object, eigenprobes and weights",
+    "c3": "config 3: 8 slices of 2048x2048, 2 probe modes of 128x128, 5000 Fermat-spiral positions, "
+          "lambda z = 81.92 px^2, amplitude loss, gradients of all slices, probe and positions",
+    "c5": "config 5 (mode-heavy): 413x535 object, 30 probe modes of 128x128, 6732 raster positions with "
+          "sub-pixel offsets, amplitude loss, gradients of object, probe and positions",
+    "c4": "config 4: 32 independent datasets (64^2-512^2 frames, 1-4 modes, 200-5000 positions each, "
+          "per-position probe amplitudes), one batched persistent launch captured in a hipGraph, amplitude loss, "
+          "gradients of objects, probes, positions and weights",
+}
+
+
+def build_workload(name):
+    import dataclasses
+
+    from synth import workloads as W
+    if name == "c1m0":
+        truth = W.make_config(1)
+        truth = dataclasses.replace(truth, probe=truth.probe[:, :1].copy())
+    else:
+        truth = W.make_config(int(name[1:]))
+    return truth, W.perturb(truth, 21)
+
+
+def kernel_name(plan, prob, tune):
+    info = plan.info()
+    loss = 1 if prob.loss == "poisson" else 0
+    if prob.N >= 256:
+        return "fused_big_kernel<%d, %d>" % (prob.N, loss)
+    if prob.S > 1:
+        return "fused_small_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
+    rv = "true" if (tune or {}).get("variant") in (2, 3) and prob.N >= 64 else "false"
+    return "fused_small_kernel<%d, %d, %d, %s>" % (prob.N, info["threads"], loss, rv)
+
+
+def measured_intensities(truth, dev, torch, t, Plan):
+    """The clean far field of the truth (computed by the library) plus Poisson noise."""
+    base = Plan.for_problem(truth)
+    I_clean = torch.empty((truth.K, truth.N, truth.N), dtype=torch.float32, device=dev)
+    w = t(truth.weights) if truth.weights is not None else None
+    base.forward(t(truth.obj), t(truth.probe), t(truth.positions), torch.zeros_like(I_clean), weights=w,
+                 I_pred=I_clean)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20931)
+    I = torch.poisson(I_clean, generator=gen).contiguous()
+    del base, I_clean
+    return I
+
+
+def run_batched(args, dev, torch, t):
+    """Config 4: one batched launch over 32 uneven datasets."""
+    from paper_2510_20929_amd import Batch, Plan
+    from synth import workloads as W
+    truths = W.make_batched_config()
+    starts = [W.perturb(p, 3) for p in truths]
+    grads = ("obj", "probe", "pos", "weights")
+    b = Batch(starts)
+    outs = []
+    for i, (tr, st) in enumerate(zip(truths, starts)):
+        I = measured_intensities(tr, dev, torch, t, Plan)
+        outs.append(b.bind(i, t(st.obj), t(st.probe), t(st.positions), I, weights=t(st.weights)))
+    for _ in range(args.warmup):
+        b.launch(grads)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.launch(grads)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    K = sum(p.K for p in truths)
+    flops = sum(algorithmic(p)[0] * p.K for p in starts)
+    byts = sum(algorithmic(p)[1] * p.K for p in starts)
+    b.launch(grads, per_call=True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(max(1, args.plain_steps)):
+        b.launch(grads, per_call=True)
+    torch.cuda.synchronize()
+    per_call_ms = (time.perf_counter() - tp0) * 1e3 / max(1, args.plain_steps)
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"value": K / (ms * 1e-3), "ms_per_step": ms, "K": K,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                         "kernel": "whole batched step (graph replay)", "kernel_ms": ms},
+            "hbm": {"alg_GBs": byts / (ms * 1e-3) / 1e9, "frac_of_peak": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "per_call": {"value": K / (per_call_ms * 1e-3), "ms_per_step": per_call_ms},
+            "batched_vs_per_call": per_call_ms / ms, "error_flags": b.get_error(),
+            "config": {"datasets": len(truths), "positions": K,
+                       "frames": sorted({p.N for p in truths}), "form": "batched persistent kernel, hipGraph replay"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS),
+                    help="synthetic workload (default: config 1, the headline measurement)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-step form")
     ap.add_argument("--tune", default=None,
@@ -128,7 +233,6 @@ def main():
     import torch
 
     from paper_2510_20929_amd import Plan
-    from synth import workloads as W
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -140,19 +244,24 @@ def main():
         print(json.dumps({"copy_bytes": x.numel() * 4}))
         return
 
-    truth = W.make_config(1)
-    start = W.perturb(truth, 21)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    common = {"metric": "diffraction patterns/s forward+adjoint at 128² frames (fused vs plain), % HBM peak",
+              "unit": "patterns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+
+    if args.workload == "c4":
+        r = run_batched(args, dev, torch, t)
+        cfg = dict(r.pop("config"))
+        cfg["workload"] = WORKLOADS["c4"]
+        line = dict(common, value=r.pop("value"), ms_per_step=r.pop("ms_per_step"), config=cfg, **r)
+        print(json.dumps(line), flush=True)
+        return
+
+    truth, start = build_workload(args.workload)
     obj, probe, pos = t(start.obj), t(start.probe), t(start.positions)
-    base = Plan.for_problem(start)
-    # measured intensities: the clean far field of the truth (computed by the library) plus Poisson noise
-    I_clean = torch.empty((truth.K, truth.N, truth.N), dtype=torch.float32, device=dev)
-    base.forward(t(truth.obj), t(truth.probe), t(truth.positions), torch.zeros_like(I_clean), I_pred=I_clean)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(20931)
-    I_meas = torch.poisson(I_clean, generator=gen).contiguous()
-    grads = ("obj", "probe", "pos")
-    del base
+    wts = t(start.weights) if start.weights is not None else None
+    I_meas = measured_intensities(truth, dev, torch, t, Plan)
+    grads = start.grads
     # implementation choice by the autotuner (parity-gated, untimed here)
     from paper_2510_20929_amd import autotune
     shape = dict(N=start.N, M=start.M, E=start.E, S=start.S, H=start.H, W=start.W, loss=start.loss, eps=start.eps,
@@ -161,14 +270,14 @@ def main():
     if args.tune:
         tune, tune_src = json.loads(args.tune), "fixed"
     else:
-        tune, rep = autotune.tune_plan(shape, obj, probe, pos, I_meas, grads=grads, cache_path=cache,
+        tune, rep = autotune.tune_plan(shape, obj, probe, pos, I_meas, weights=wts, grads=grads, cache_path=cache,
                                        use_cache=not args.retune)
         tune_src = "cache" if rep.get("cached") else "autotuned"
     plan = Plan.for_problem(start, tune=tune)
-    out = plan.forward_adjoint(obj, probe, pos, I_meas, grads=grads)
+    out = plan.forward_adjoint(obj, probe, pos, I_meas, weights=wts, grads=grads)
 
     def step(plain=False):
-        plan.forward_adjoint(obj, probe, pos, I_meas, grads=grads, out=out, plain=plain)
+        plan.forward_adjoint(obj, probe, pos, I_meas, weights=wts, grads=grads, out=out, plain=plain)
 
     for _ in range(args.warmup):
         step()
@@ -187,13 +296,16 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     K = truth.K
     value = K / (ms_step * 1e-3)
-    k_avg_ms = k_ms / max(k_n, 1)
+    k_avg_ms = k_ms / max(k_n, 1)          # one launch (a chunk of positions)
+    launches = max(k_n, 1) / args.steps     # launches per step (positions are chunked when the
+    k_step_ms = k_ms / args.steps           # window buffer would exceed its budget)
 
     flops_pp, bytes_pp = algorithmic(start)
-    achieved_tflops = flops_pp * K / (k_avg_ms * 1e-3) / 1e12
-    hbm_alg_gbs = bytes_pp * K / (k_avg_ms * 1e-3) / 1e9
+    achieved_tflops = flops_pp * K / (k_step_ms * 1e-3) / 1e12
+    hbm_alg_gbs = bytes_pp * K / (k_step_ms * 1e-3) / 1e9
     khash = kernel_hash()
-    traffic = read_traffic(khash)
+    headline = args.workload == "c1"
+    traffic = read_traffic(khash, kernel_name(plan, start, tune)) if headline else None
 
     plain = None
     if not args.no_plain:
@@ -214,32 +326,21 @@ def main():
                  "hbm_alg_frac": bytes_pp * K / (p_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     cpu = None
-    if not args.no_cpu:
+    if headline and not args.no_cpu:
         cpu = cpu_baseline(truth, start)
 
-    line = {
-        "metric": "diffraction patterns/s forward+adjoint at 128² frames (fused vs plain), % HBM peak",
+    line = dict(common)
+    line.update({
         "value": value,
-        "unit": "patterns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "config 1: 1024x1024 complex object, 4 Hermite-Gauss probe modes of 128x128, "
-                               "2000 Fermat-spiral positions with sub-pixel offsets, Poisson loss, gradients "
-                               "of object, probe and positions",
-                   "frame": 128, "modes": 4, "positions": K, "object": [1024, 1024], "loss": "poisson",
-                   "form": "fused persistent kernel"},
+        "config": {"workload": WORKLOADS[args.workload], "frame": start.N, "modes": start.M,
+                   "eigenprobes": start.E, "slices": start.S, "positions": K, "object": [start.H, start.W],
+                   "loss": start.loss, "form": "fused persistent kernel"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "fused_small_kernel<128, %d, 1, %s>" % (plan.info()["threads"],
-                                                                      "true" if tune.get("variant") in (2, 3) else "false"),
-                     "kernel_ms": k_avg_ms, "flops_per_pattern": flops_pp},
+                     "traffic": traffic, "kernel": kernel_name(plan, start, tune),
+                     "kernel_ms": k_avg_ms, "launches_per_step": launches, "kernel_ms_per_step": k_step_ms,
+                     "flops_per_pattern": flops_pp},
         "hbm": {"alg_bytes_per_pattern": bytes_pp, "alg_GBs": hbm_alg_gbs, "frac_of_peak": hbm_alg_gbs / HBM_PEAK_GBS},
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
@@ -248,7 +349,7 @@ def main():
         "tune_source": tune_src,
         "error_flags": flags,
         "kernel_hash": khash,
-    }
+    })
     print(json.dumps(line), flush=True)
 
 

@@ -1,4 +1,4 @@
-"""Seeded synthetic ptychography workloads (configs 0-4) and noise draws.
+"""Seeded synthetic ptychography workloads (configs 0-5) and noise draws.
 
 Everything here is input preparation: smooth random objects, probe shapes,
 scan geometries, the perturbation that moves a problem off its truth, and
@@ -247,10 +247,41 @@ def _config3(rng, S: int, H: int, K: int) -> Problem:
                    "amplitude", lambda_z=fresnel_number_lambda_z(N), grads=("obj", "probe", "pos"))
 
 
+def _mode_orders(M: int):
+    """The first M Hermite-Gauss orders (m, n), by total order m + n, then by m."""
+    orders = []
+    tot = 0
+    while len(orders) < M:
+        for m in range(tot, -1, -1):
+            orders.append((m, tot - m))
+        tot += 1
+    return orders[:M]
+
+
+def _config5(rng, H: int, W: int, K: int, M: int) -> Problem:
+    """Mode-heavy workload shaped like the paper's benchmark dataset: 6732 diffraction
+    patterns of 128^2, a 413 x 535 object and 30 probe modes (no OPR). The probe modes
+    are orthonormalised Hermite-Gauss modes with powers decaying as exp(-j / 6); the scan
+    is a 68 x 99 raster covering the object (step about 4.1 px) with sub-pixel offsets."""
+    N = 128
+    obj = random_object(rng, H, W)[None]
+    powers = np.exp(-np.arange(M) / 6.0)
+    powers = powers / powers.sum()
+    modes = _hg_modes(N, _mode_orders(M), 16.0, powers, 32.0)
+    ny, nx = 68, 99
+    step = min((H - N - 2) / (ny - 1), (W - N - 2) / (nx - 1))
+    pos = raster(ny, nx, step) + rng.uniform(0.0, 1.0, size=(ny * nx, 2))
+    pos = pos[:K]
+    probe = modes[None] * _photon_scale(modes, obj, PHOTONS_PER_FRAME)
+    return Problem("c5", obj, probe.astype(np.complex64), pos.astype(np.float32), None,
+                   "amplitude", grads=("obj", "probe", "pos"))
+
+
 def make_config(c: int, *, H: Optional[int] = None, K: Optional[int] = None,
-                S: Optional[int] = None) -> Problem:
-    """Truth problem for config ``c`` (0-3). H, K, S shrink it for tests while keeping
-    the frame size, the mode/eigenprobe structure and the scan pattern."""
+                S: Optional[int] = None, W: Optional[int] = None, M: Optional[int] = None) -> Problem:
+    """Truth problem for config ``c`` (0-3, 5). H, K, S shrink it for tests while keeping
+    the frame size, the mode/eigenprobe structure and the scan pattern (config 5 also
+    takes W and the mode count M)."""
     rng = np.random.default_rng(SEED_BASE + c)
     if c == 0:
         return _config0(rng, H or 256, K)
@@ -260,6 +291,8 @@ def make_config(c: int, *, H: Optional[int] = None, K: Optional[int] = None,
         return _config2(rng, H or 2048, K or 10000)
     if c == 3:
         return _config3(rng, S or 8, H or 2048, K or 5000)
+    if c == 5:
+        return _config5(rng, H or 413, W or 535, K or 6732, M or 30)
     raise ValueError(f"unknown config {c}")
 
 

@@ -327,7 +327,7 @@ def test_batched_equals_sum_of_single_positions_and_shards():
 # ----------------------------------------------------------------------------- synthetic inputs
 
 def test_synthetic_configs_shapes_and_bounds():
-    for c, kw in [(0, {}), (1, {}), (2, dict(H=700, K=400)), (3, dict(H=400, K=200, S=2))]:
+    for c, kw in [(0, {}), (1, {}), (2, dict(H=700, K=400)), (3, dict(H=400, K=200, S=2)), (5, {})]:
         p = W.make_config(c, **kw)
         assert p.positions.dtype == np.float32 and p.obj.dtype == np.complex64
         assert p.positions.min() >= 0
@@ -341,3 +341,11 @@ def test_synthetic_configs_shapes_and_bounds():
     assert p1.K == 2000 and p1.M == 4 and p1.H == 1024
     pw = np.sum(np.abs(p1.probe[0].astype(complex)) ** 2, axis=(1, 2))
     np.testing.assert_allclose(pw / pw.sum(), [0.7, 0.15, 0.1, 0.05], rtol=1e-5)
+    p5 = W.make_config(5)
+    assert (p5.K, p5.M, p5.N, p5.H, p5.W) == (6732, 30, 128, 413, 535)
+    U = p5.probe[0].reshape(30, -1).astype(complex)
+    G = U.conj() @ U.T
+    off = np.abs(G - np.diag(np.diag(G))).max() / np.abs(np.diag(G)).max()
+    assert off < 1e-5  # orthogonal modes
+    d = np.diag(G).real
+    np.testing.assert_allclose(d[1:] / d[:-1], np.exp(-1.0 / 6.0), rtol=1e-4)  # exp(-j/6) powers

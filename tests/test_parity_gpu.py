@@ -100,3 +100,15 @@ def test_fused_variants(N, variant, recompute):
     got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute}), start, I, grads)
     compare(got, ref, grads, tag=f"N={N} variant={variant} recompute={recompute}")
     assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_config5_mode_heavy(plain):
+    """Config 5 structure (30 probe modes of 128^2, 413 x 535 object, raster with sub-pixel
+    offsets, amplitude loss) on its full object and probe with 48 positions."""
+    start, I = case(5, K=48)
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads, plain=plain)
+    compare(got, ref, grads, tag=f"c5 {'plain' if plain else 'fused'}")
+    assert got["flags"] == 0
