@@ -160,6 +160,28 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
                               const float* probe, const float* weights, const float* positions, float* g_obj,
                               float* g_probe);
 
+/* Illumination map in the object frame: the probe intensity of every scan position
+ * superimposed where it falls, illum[y][x] = sum_k S_k^T (sum_m |P_k,m|^2), with S_k^T
+ * the transpose of the bilinear patch extraction (the scatter used for the object
+ * gradient) and P_k,m = sum_e w_k,e U_e,m. This is the object preconditioner of the
+ * least-squares reconstructor (Introduction: the illumination superimposed in the
+ * object frame; Performance benchmarking: the cost of building it).
+ *   probe [E][M][N][N] complex, weights [K][E] or NULL (E == 1), positions [K][2]
+ *   illum [H][W] float, overwritten, or added to with PTYHIP_ACCUMULATE (the only flag)
+ * Positions whose window leaves the object contribute nothing and set the error
+ * latch, as in ptyhip_forward_adjoint. */
+ptyhip_status ptyhip_illumination(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* probe,
+                                  const float* weights, const float* positions, float* illum);
+
+/* Scale-normalised gradients (Reconstructors: the ePIE-style treatment of the gradient
+ * after Eq. (2)): g_obj *= K_norm N^2 / max_{k,p} sum_m |P_k,m(p)|^2 and, read the same
+ * way for the probe, g_probe *= K_norm N^2 / max |O|^2 (over every object pixel).
+ * K_norm is the plan's norm_count, or K when that is <= 0. Either gradient may be NULL
+ * (then it is left alone); K >= 1. The maxima are computed on the device; a zero
+ * maximum leaves the gradient unchanged. In place, asynchronous on `stream`. */
+ptyhip_status ptyhip_normalize_gradients(ptyhip_plan plan, void* stream, int32_t K, const float* probe,
+                                         const float* weights, const float* obj, float* g_obj, float* g_probe);
+
 /* Kernel timing: when enabled, every call records a pair of HIP events on its stream
  * immediately around its main kernel (the fused kernel, or the whole per-step chain).
  * ptyhip_plan_kernel_time waits for those events, returns the summed milliseconds and

@@ -19,10 +19,13 @@ from .ptycho_ref import (  # noqa: F401
     forward_adjoint,
     fresnel_tf,
     ifft2u,
+    illumination,
     loss_and_factor,
+    normalized_gradients,
     patch_derivatives,
     patch_gradients,
     probe_for_position,
+    probe_power_max,
     propagate,
     scatter_patch,
     split_position,

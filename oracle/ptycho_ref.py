@@ -358,3 +358,52 @@ def patch_gradients(obj, probe, positions, I_meas, *, weights=None, loss="amplit
         for s in range(S):
             out[k, s] = g_patch[s]
     return out
+
+
+# ----------------------------------------------------------------------------- preconditioner and scaling
+
+def illumination(probe, positions, H: int, W: int, *, weights=None) -> np.ndarray:
+    """Illumination in the object frame [H, W]: for every position, the probe intensity
+    summed over modes, sum_m |P_{k,m}|^2, put back into the object frame by the
+    transpose of the bilinear patch extraction, summed over positions. This is the
+    object preconditioner built by superimposing the illumination function in the
+    object frame (Introduction; its cost is discussed under Performance benchmarking)."""
+    U = np.asarray(probe, dtype=np.complex128)
+    N = U.shape[-1]
+    pos = np.asarray(positions, dtype=np.float64)
+    out = np.zeros((H, W), dtype=np.float64)
+    for k in range(pos.shape[0]):
+        w_k = None if weights is None else np.asarray(weights[k], dtype=np.float64)
+        P = probe_for_position(U, w_k)
+        A = np.sum(P.real ** 2 + P.imag ** 2, axis=0)
+        y0, x0, fy, fx = split_position(pos[k], N, H, W, False)
+        scatter_patch(out, A, y0, x0, fy, fx)
+    return out
+
+
+def probe_power_max(probe, K: int, *, weights=None) -> float:
+    """max over positions and pixels of sum_m |P_{k,m}|^2."""
+    U = np.asarray(probe, dtype=np.complex128)
+    best = 0.0
+    for k in range(K if weights is not None else 1):
+        w_k = None if weights is None else np.asarray(weights[k], dtype=np.float64)
+        P = probe_for_position(U, w_k)
+        best = max(best, float(np.max(np.sum(np.abs(P) ** 2, axis=0))))
+    return best
+
+
+def normalized_gradients(g_obj, g_probe, obj, probe, K: int, *, weights=None, norm_count=None):
+    """Scale-normalised gradients (Reconstructors, after Eq. (2)): the object gradient
+    times B H W / max |p|^2, with B H W = K_norm N^2 here and max |p|^2 the largest
+    mode-summed probe intensity; the probe gradient, read the same way, times
+    K_norm N^2 / max |O|^2. A zero maximum leaves a gradient unchanged."""
+    N = np.asarray(probe).shape[-1]
+    c = float(norm_count if norm_count else K) * N * N
+    go = gp = None
+    if g_obj is not None:
+        pm = probe_power_max(probe, K, weights=weights)
+        go = np.asarray(g_obj, dtype=np.complex128) * (c / pm if pm > 0 else 1.0)
+    if g_probe is not None:
+        om = float(np.max(np.abs(np.asarray(obj, dtype=np.complex128)) ** 2))
+        gp = np.asarray(g_probe, dtype=np.complex128) * (c / om if om > 0 else 1.0)
+    return go, gp

@@ -23,6 +23,7 @@ SOURCES = [
     "kernels/finalize.hip",
     "kernels/gather.hip",
     "kernels/batched.hip",
+    "kernels/illum.hip",
     "host/abi.cpp",
     "host/batch.cpp",
 ]

@@ -154,6 +154,10 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if ((st = dalloc(p, &p->cbuf, C * NN)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->valid, C)) != PTYHIP_OK) return st;
   p->plain_bytes = p->bytes - before;
+
+  // illumination map / normalised gradients
+  if ((st = dalloc(p, &p->illum_g, size_t(E) * (E + 1) / 2 * NN)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->maxima, 2)) != PTYHIP_OK) return st;
   return PTYHIP_OK;
 }
 
@@ -446,6 +450,81 @@ ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, 
                                      float* g_probe, float* g_pos, float* g_weights) {
   return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K, flags, obj, probe,
                               weights, positions, I_meas, loss, I_pred, g_obj, g_probe, g_pos, g_weights, false);
+}
+
+ptyhip_status ptyhip_illumination(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* probe,
+                                  const float* weights, const float* positions, float* illum) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
+  if (!probe || !illum || (K > 0 && !positions)) return PTYHIP_EINVAL;
+  if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
+  if (flags & ~uint32_t(PTYHIP_ACCUMULATE)) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ptyhip_desc& d = p->d;
+  const int N = d.frame, E = d.n_eig, WN = N + 1;
+  const bool acc = (flags & PTYHIP_ACCUMULATE) != 0;
+  if (K == 0) {
+    if (!acc && launch_fill(illum, size_t(d.obj_h) * d.obj_w, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
+    return PTYHIP_OK;
+  }
+  if (launch_illum_gram(reinterpret_cast<const float2*>(probe), E, d.n_modes, N, p->illum_g, st) != hipSuccess)
+    return PTYHIP_EHIP;
+  // the window buffer holds [fchunk][N+1]^2 windows followed by [fchunk][N][N] intensities
+  float* wbuf = reinterpret_cast<float*>(p->gwin);
+  for (int k0 = 0; k0 < K; k0 += p->fchunk) {
+    IllumArgs a{};
+    a.G = p->illum_g;
+    a.G0 = p->illum_g;
+    a.w = weights;
+    a.pos = positions;
+    a.win = wbuf;
+    a.Ak = (E > 1) ? wbuf + size_t(p->fchunk) * WN * WN : nullptr;
+    a.wvalid = p->wvalid;
+    a.illum = illum;
+    a.flags = p->flags;
+    a.k0 = k0;
+    a.n = std::min(p->fchunk, K - k0);
+    a.E = E;
+    a.N = N;
+    a.H = d.obj_h;
+    a.W = d.obj_w;
+    a.accumulate = (acc || k0 > 0) ? 1 : 0;
+    if (launch_illum_chunk(a, 4 * p->cus, st) != hipSuccess) return PTYHIP_EHIP;
+  }
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_normalize_gradients(ptyhip_plan plan, void* stream, int32_t K, const float* probe,
+                                         const float* weights, const float* obj, float* g_obj, float* g_probe) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (K < 1 || K > p->maxK) return PTYHIP_EBOUNDS;
+  if (g_obj && !probe) return PTYHIP_EINVAL;
+  if (g_probe && !obj) return PTYHIP_EINVAL;
+  if (g_obj && p->d.n_eig > 1 && !weights) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const ptyhip_desc& d = p->d;
+  const int N = d.frame, E = d.n_eig;
+  const double knorm = d.norm_count > 0.0 ? d.norm_count : double(K);
+  const double c = knorm * double(N) * double(N);
+  if (launch_zero_u32(p->maxima, 2, st) != hipSuccess) return PTYHIP_EHIP;
+  if (g_obj) {
+    if (launch_illum_gram(reinterpret_cast<const float2*>(probe), E, d.n_modes, N, p->illum_g, st) != hipSuccess)
+      return PTYHIP_EHIP;
+    if (launch_power_max(p->illum_g, weights, E, N, K, p->maxima, st) != hipSuccess) return PTYHIP_EHIP;
+    if (launch_scale_by_max(reinterpret_cast<float2*>(g_obj), p->obj_elems, c, p->maxima, st) != hipSuccess)
+      return PTYHIP_EHIP;
+  }
+  if (g_probe) {
+    if (launch_abs2_max(reinterpret_cast<const float2*>(obj), p->obj_elems, p->maxima + 1, st) != hipSuccess)
+      return PTYHIP_EHIP;
+    if (launch_scale_by_max(reinterpret_cast<float2*>(g_probe), p->probe_elems, c, p->maxima + 1, st) != hipSuccess)
+      return PTYHIP_EHIP;
+  }
+  return PTYHIP_OK;
 }
 
 ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,

@@ -51,6 +51,9 @@ struct Plan {
   float* cbuf = nullptr;
   int* valid = nullptr;
   size_t plain_bytes = 0;
+  // illumination map and normalised gradients
+  float* illum_g = nullptr;   // [E(E+1)/2][N][N] probe Gram terms
+  unsigned* maxima = nullptr; // [2] device maxima (probe intensity, object intensity)
   // kernel timing (events recorded around the main kernel of each call)
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;

@@ -13,28 +13,39 @@ namespace ptyhip {
 
 constexpr int GT = 32;  // tile side
 
+__device__ __forceinline__ float vadd(float a, float b) { return a + b; }
+__device__ __forceinline__ float2 vadd(float2 a, float2 b) { return cadd(a, b); }
+template <class V> __device__ __forceinline__ V vzero();
+template <> __device__ __forceinline__ float vzero<float>() { return 0.f; }
+template <> __device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+
 // One 32 x 32 tile (blockIdx.x, blockIdx.y) of slice blockIdx.z; 256 threads (4 waves).
 // Positions are taken in chunks: every thread tests a few positions for overlap with the
 // tile, the hits are compacted in position order (wave ballots + a block prefix, so the
 // order never depends on timing), and then each thread adds the window values of the
 // hits at its 4 pixels, issuing the loads of 4 hits before adding them in order.
-__device__ __forceinline__ void gather_tile(const GatherArgs& g) {
+// `win` holds [K][S][N+1][N+1] windows of value type V (float2 gradients, float
+// illumination), `out` the [S][H][W] result.
+template <class V>
+__device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const int* __restrict__ wvalid,
+                                              const float* __restrict__ pos, V* out_all, int K, int S, int N,
+                                              int H, int W, int accumulate) {
   constexpr int CH = 1024;  // positions examined per chunk
   constexpr int NT = 256;
   __shared__ int hy[CH], hx[CH], hk[CH];
   __shared__ int wcnt[NT / 64];
-  const int WN = g.N + 1;
+  const int WN = N + 1;
   const int tx0 = blockIdx.x * GT, ty0 = blockIdx.y * GT, s = blockIdx.z;
   const int c = threadIdx.x % GT, r0 = threadIdx.x / GT;  // 8 rows per pass, 4 passes
   const int x = tx0 + c;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float2 acc[4];
+  V acc[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = make_float2(0.f, 0.f);
+  for (int j = 0; j < 4; ++j) acc[j] = vzero<V>();
   const size_t wsz = size_t(WN) * WN;
-  const float2 z = make_float2(0.f, 0.f);
-  for (int k0 = 0; k0 < g.K; k0 += CH) {
-    const int n = min(CH, g.K - k0);
+  const V z = vzero<V>();
+  for (int k0 = 0; k0 < K; k0 += CH) {
+    const int n = min(CH, K - k0);
     int nh = 0;
     __syncthreads();  // the previous chunk's hits are consumed
     for (int r = 0; r < CH / NT; ++r) {
@@ -42,9 +53,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g) {
       const int k = k0 + i;
       int y0 = 0, x0 = 0;
       bool hit = false;
-      if (i < n && g.wvalid[k]) {
-        y0 = int(floorf(g.pos[2 * k]));
-        x0 = int(floorf(g.pos[2 * k + 1]));
+      if (i < n && wvalid[k]) {
+        y0 = int(floorf(pos[2 * k]));
+        x0 = int(floorf(pos[2 * k + 1]));
         hit = !(y0 > ty0 + GT - 1 || y0 + WN - 1 < ty0 || x0 > tx0 + GT - 1 || x0 + WN - 1 < tx0);
       }
       const unsigned long long b = __ballot(hit);
@@ -66,13 +77,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g) {
       __syncthreads();  // wcnt is rewritten by the next round; the hits are visible
     }
     for (int h = 0; h < nh; h += 4) {
-      float2 t[4][4];
+      V t[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool on = h + u < nh;
         const int hh = on ? h + u : nh - 1;  // in-range LDS slot also for the unused tail
         const int y0 = hy[hh], px = on ? x - hx[hh] : -1;
-        const float2* w = g.gwin + (size_t(hk[hh]) * g.S + s) * wsz;
+        const V* w = win + (size_t(hk[hh]) * S + s) * wsz;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int py = ty0 + r0 + 8 * j - y0;
@@ -82,19 +93,23 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = cadd(acc[j], t[u][j]);
+        for (int j = 0; j < 4; ++j) acc[j] = vadd(acc[j], t[u][j]);
     }
   }
-  if (x >= g.W) return;
-  float2* out = g.gobj + size_t(s) * g.H * g.W;
+  if (x >= W) return;
+  V* out = out_all + size_t(s) * H * W;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int y = ty0 + r0 + 8 * j;
-    if (y < g.H) {
-      float2* o = out + size_t(y) * g.W + x;
-      *o = g.accumulate ? cadd(*o, acc[j]) : acc[j];
+    if (y < H) {
+      V* o = out + size_t(y) * W + x;
+      *o = accumulate ? vadd(*o, acc[j]) : acc[j];
     }
   }
+}
+
+__device__ __forceinline__ void gather_tile(const GatherArgs& g) {
+  gather_tile_t<float2>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate);
 }
 
 }  // namespace ptyhip

@@ -36,6 +36,21 @@ struct FinalArgs {
 };
 
 // Gather of the per-position window gradients into the object gradient.
+// One chunk of positions [k0, k0 + n) of the illumination map.
+struct IllumArgs {
+  const float* G;       // [E(E+1)/2][N][N] probe Gram terms
+  const float* G0;      // G's first frame (one eigenprobe)
+  const float* w;       // [K][E] weights or nullptr
+  const float* pos;     // [K][2]
+  float* Ak;            // [n][N][N] per-position intensity (several eigenprobes) or nullptr
+  float* win;           // [n][N+1][N+1]
+  int* wvalid;          // [n]
+  float* illum;         // [H][W]
+  uint32_t* flags;
+  int k0, n, E, N, H, W;
+  int accumulate;
+};
+
 struct GatherArgs {
   const float2* gwin;  // [K][S][N+1][N+1]
   const int* wvalid;   // [K]
@@ -62,6 +77,12 @@ hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g
                                    hipStream_t st);
 
 hipError_t launch_finalize(const FinalArgs& f, hipStream_t st);
+hipError_t launch_illum_gram(const float2* U, int E, int M, int N, float* G, hipStream_t st);
+hipError_t launch_illum_chunk(const IllumArgs& a, int grid, hipStream_t st);
+hipError_t launch_power_max(const float* G, const float* w, int E, int N, int K, unsigned* out, hipStream_t st);
+hipError_t launch_abs2_max(const float2* x, size_t n, unsigned* out, hipStream_t st);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
+hipError_t launch_scale_by_max(float2* x, size_t n, double c, const unsigned* mx, hipStream_t st);
 
 // One dataset of a batched launch, as the device reads it from the descriptor table.
 struct BatchEntry {

@@ -32,7 +32,7 @@ STATUS = {0: "PTYHIP_OK", 1: "PTYHIP_EINVAL", 2: "PTYHIP_ESHAPE", 3: "PTYHIP_EBO
 EXPORTED = [
     "ptyhip_status_str", "ptyhip_version", "ptyhip_desc_validate", "ptyhip_plan_create", "ptyhip_plan_create_ex",
     "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint", "ptyhip_apply_A",
-    "ptyhip_apply_AH", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
+    "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
     "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
     "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy",
 ]
@@ -276,6 +276,36 @@ class Plan:
         st = _lib().ptyhip_apply_AH(self._h, _stream(stream), K, _ptr(Y), _ptr(obj), _ptr(probe), _ptr(weights),
                                     _ptr(positions), _ptr(g_obj), _ptr(g_probe))
         _check(st, "ptyhip_apply_AH")
+        return g_obj, g_probe
+
+    def illumination(self, probe, positions, weights=None, out=None, accumulate=False, stream=None):
+        """Probe intensity superimposed in the object frame, [H][W] float32."""
+        K = int(positions.shape[0])
+        _need(probe, "probe", torch.complex64, (self.E, self.M, self.N, self.N))
+        _need(positions, "positions", torch.float32, (K, 2))
+        if weights is not None:
+            _need(weights, "weights", torch.float32, (K, self.E))
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.float32, device=probe.device)
+        _need(out, "illum", torch.float32, (self.H, self.W))
+        st = _lib().ptyhip_illumination(self._h, _stream(stream), K, ACCUMULATE if accumulate else 0, _ptr(probe),
+                                        _ptr(weights), _ptr(positions), _ptr(out))
+        _check(st, "ptyhip_illumination")
+        return out
+
+    def normalize_gradients(self, K, probe=None, obj=None, weights=None, g_obj=None, g_probe=None, stream=None):
+        """In place: g_obj *= K_norm N^2 / max probe intensity, g_probe *= K_norm N^2 / max |O|^2."""
+        if g_obj is not None:
+            _need(g_obj, "g_obj", torch.complex64, (self.S, self.H, self.W))
+            _need(probe, "probe", torch.complex64, (self.E, self.M, self.N, self.N))
+        if g_probe is not None:
+            _need(g_probe, "g_probe", torch.complex64, (self.E, self.M, self.N, self.N))
+            _need(obj, "obj", torch.complex64, (self.S, self.H, self.W))
+        if weights is not None:
+            _need(weights, "weights", torch.float32, (int(K), self.E))
+        st = _lib().ptyhip_normalize_gradients(self._h, _stream(stream), int(K), _ptr(probe), _ptr(weights),
+                                               _ptr(obj), _ptr(g_obj), _ptr(g_probe))
+        _check(st, "ptyhip_normalize_gradients")
         return g_obj, g_probe
 
     def set_timing(self, enable: bool = True):
