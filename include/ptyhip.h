@@ -182,6 +182,18 @@ ptyhip_status ptyhip_illumination(ptyhip_plan plan, void* stream, int32_t K, uin
 ptyhip_status ptyhip_normalize_gradients(ptyhip_plan plan, void* stream, int32_t K, const float* probe,
                                          const float* weights, const float* obj, float* g_obj, float* g_probe);
 
+/* Probe-mode orthogonalisation, one of the parameter routines shared by every
+ * reconstructor (Software design, Overview). The modes of eigenprobe 0 are replaced by
+ * the eigenmodes of their Gram matrix G_mn = sum_p conj(P_m(p)) P_n(p) = V diag(l) V^H,
+ * strongest first: P'_j = sum_m V_mj P_m. The same unitary is applied to every
+ * eigenprobe, so sum_m |P_k,m|^2 and the forward model are unchanged. Each column of V
+ * has its largest-magnitude entry (the first on ties) made real and positive.
+ *   probe, probe_out [E][M][N][N] complex (out of place: the two may not overlap)
+ *   powers           device double[M] (l_j = ||P'_j||^2, descending) or NULL
+ * Gram sums and the Jacobi eigen-solver run in FP64 on the device. */
+ptyhip_status ptyhip_orthogonalize_modes(ptyhip_plan plan, void* stream, const float* probe, float* probe_out,
+                                         double* powers);
+
 /* Kernel timing: when enabled, every call records a pair of HIP events on its stream
  * immediately around its main kernel (the fused kernel, or the whole per-step chain).
  * ptyhip_plan_kernel_time waits for those events, returns the summed milliseconds and

@@ -22,6 +22,7 @@ from .ptycho_ref import (  # noqa: F401
     illumination,
     loss_and_factor,
     normalized_gradients,
+    orthogonalize_modes,
     patch_derivatives,
     patch_gradients,
     probe_for_position,

@@ -407,3 +407,28 @@ def normalized_gradients(g_obj, g_probe, obj, probe, K: int, *, weights=None, no
         om = float(np.max(np.abs(np.asarray(obj, dtype=np.complex128)) ** 2))
         gp = np.asarray(g_probe, dtype=np.complex128) * (c / om if om > 0 else 1.0)
     return go, gp
+
+
+# ----------------------------------------------------------------------------- probe modes
+
+def orthogonalize_modes(probe):
+    """Probe-mode orthogonalisation (a shared parameter routine, Software design /
+    Overview): eigen-decomposition of the Gram matrix of eigenprobe 0's modes,
+    G_mn = <P_m, P_n> = V diag(l) V^H, new modes P'_j = sum_m V_mj P_m with the
+    eigenvalues in decreasing order (ties by index), the same V applied to every
+    eigenprobe, and each column of V phased so that its largest-magnitude entry (the
+    first on ties) is real and positive. Returns (new probe [E, M, N, N], l [M])."""
+    U = np.asarray(probe, dtype=np.complex128)
+    E, M = U.shape[:2]
+    X = U[0].reshape(M, -1)
+    G = X.conj() @ X.T
+    lam, V = np.linalg.eigh(G)
+    order = sorted(range(M), key=lambda j: (-lam[j], j))
+    lam = lam[order]
+    V = V[:, order]
+    for j in range(M):
+        a = np.abs(V[:, j])
+        m = int(np.argmax(a))
+        V[:, j] *= np.conj(V[m, j]) / a[m]
+    out = np.einsum("mj,emab->ejab", V, U)
+    return out, lam

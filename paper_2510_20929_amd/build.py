@@ -24,6 +24,7 @@ SOURCES = [
     "kernels/gather.hip",
     "kernels/batched.hip",
     "kernels/illum.hip",
+    "kernels/modes.hip",
     "host/abi.cpp",
     "host/batch.cpp",
 ]

@@ -158,6 +158,9 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   // illumination map / normalised gradients
   if ((st = dalloc(p, &p->illum_g, size_t(E) * (E + 1) / 2 * NN)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->maxima, 2)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->mode_gram, size_t(M) * M * 2)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->mode_vec, size_t(M) * M * 2)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->mode_pow, size_t(M))) != PTYHIP_OK) return st;
   return PTYHIP_OK;
 }
 
@@ -524,6 +527,24 @@ ptyhip_status ptyhip_normalize_gradients(ptyhip_plan plan, void* stream, int32_t
     if (launch_scale_by_max(reinterpret_cast<float2*>(g_probe), p->probe_elems, c, p->maxima + 1, st) != hipSuccess)
       return PTYHIP_EHIP;
   }
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_orthogonalize_modes(ptyhip_plan plan, void* stream, const float* probe, float* probe_out,
+                                         double* powers) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p || !probe || !probe_out) return PTYHIP_EINVAL;
+  const ptyhip_desc& d = p->d;
+  const size_t bytes = p->probe_elems * sizeof(float2);
+  const char* a0 = reinterpret_cast<const char*>(probe);
+  const char* b0 = reinterpret_cast<const char*>(probe_out);
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return PTYHIP_EINVAL;  // out-of-place only
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (launch_mode_orthogonalize(reinterpret_cast<const float2*>(probe), d.n_eig, d.n_modes, d.frame, p->mode_gram,
+                                p->mode_vec, powers ? powers : p->mode_pow,
+                                reinterpret_cast<float2*>(probe_out), st) != hipSuccess)
+    return PTYHIP_EHIP;
   return PTYHIP_OK;
 }
 

@@ -54,6 +54,10 @@ struct Plan {
   // illumination map and normalised gradients
   float* illum_g = nullptr;   // [E(E+1)/2][N][N] probe Gram terms
   unsigned* maxima = nullptr; // [2] device maxima (probe intensity, object intensity)
+  // probe-mode orthogonalisation: Gram matrix, eigenvectors (complex FP64), eigenvalues
+  double* mode_gram = nullptr;  // [M][M][2]
+  double* mode_vec = nullptr;   // [M][M][2]
+  double* mode_pow = nullptr;   // [M]
   // kernel timing (events recorded around the main kernel of each call)
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;

@@ -82,6 +82,8 @@ hipError_t launch_illum_chunk(const IllumArgs& a, int grid, hipStream_t st);
 hipError_t launch_power_max(const float* G, const float* w, int E, int N, int K, unsigned* out, hipStream_t st);
 hipError_t launch_abs2_max(const float2* x, size_t n, unsigned* out, hipStream_t st);
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
+hipError_t launch_mode_orthogonalize(const float2* U, int E, int M, int N, void* gram, void* vmat, double* lam,
+                                     float2* out, hipStream_t st);
 hipError_t launch_scale_by_max(float2* x, size_t n, double c, const unsigned* mx, hipStream_t st);
 
 // One dataset of a batched launch, as the device reads it from the descriptor table.

@@ -32,7 +32,8 @@ STATUS = {0: "PTYHIP_OK", 1: "PTYHIP_EINVAL", 2: "PTYHIP_ESHAPE", 3: "PTYHIP_EBO
 EXPORTED = [
     "ptyhip_status_str", "ptyhip_version", "ptyhip_desc_validate", "ptyhip_plan_create", "ptyhip_plan_create_ex",
     "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint", "ptyhip_apply_A",
-    "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
+    "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients",
+    "ptyhip_orthogonalize_modes", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
     "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
     "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy",
 ]
@@ -307,6 +308,17 @@ class Plan:
                                                _ptr(obj), _ptr(g_obj), _ptr(g_probe))
         _check(st, "ptyhip_normalize_gradients")
         return g_obj, g_probe
+
+    def orthogonalize_modes(self, probe, out=None, stream=None):
+        """Orthogonalised probe modes (strongest first) and their powers (float64 [M])."""
+        _need(probe, "probe", torch.complex64, (self.E, self.M, self.N, self.N))
+        if out is None:
+            out = torch.empty_like(probe)
+        _need(out, "probe_out", torch.complex64, (self.E, self.M, self.N, self.N))
+        powers = torch.empty(self.M, dtype=torch.float64, device=probe.device)
+        st = _lib().ptyhip_orthogonalize_modes(self._h, _stream(stream), _ptr(probe), _ptr(out), _ptr(powers))
+        _check(st, "ptyhip_orthogonalize_modes")
+        return out, powers
 
     def set_timing(self, enable: bool = True):
         _check(_lib().ptyhip_plan_set_timing(self._h, 1 if enable else 0), "ptyhip_plan_set_timing")
