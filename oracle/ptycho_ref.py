@@ -255,18 +255,28 @@ def apply_AH(Y, obj, probe, positions, weights=None, lambda_z: float = 0.0):
 
 
 def forward(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
-            eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None):
-    """Loss L and the predicted intensity I_pred [K, N, N] (DC-centred)."""
+            eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None,
+            det_lambda_z: Optional[float] = None):
+    """Loss L and the predicted intensity I_pred [K, N, N] (DC-centred in the far field,
+    natural pixel order in the near field)."""
     out = forward_adjoint(obj, probe, positions, I_meas, weights=weights, loss=loss, eps=eps,
-                          lambda_z=lambda_z, norm_count=norm_count, grads=())
+                          lambda_z=lambda_z, norm_count=norm_count, grads=(), det_lambda_z=det_lambda_z)
     return out["loss"], out["I_pred"]
 
 
 def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
                     eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None,
-                    grads: Sequence[str] = ("obj", "probe")) -> Dict[str, np.ndarray]:
+                    grads: Sequence[str] = ("obj", "probe"),
+                    det_lambda_z: Optional[float] = None) -> Dict[str, np.ndarray]:
     """Loss, predicted intensity and the requested gradients
-    (any of "obj", "probe", "pos", "weights")."""
+    (any of "obj", "probe", "pos", "weights", and "lambda_z" in the near field).
+
+    Near field (det_lambda_z given; the propagation variant of the forward model, Software
+    design, Overview): the last exit wave chi is carried to the detector by Fresnel
+    propagation, Psi = F^-1(H F chi) with H = exp(-i pi lz_det (fy^2 + fx^2)), instead of
+    the far-field transform; the detector is in natural pixel order. "lambda_z" asks for
+    dL/d(lz_det) = sum_k,m Re sum_f conj(F g_Psi) (-i pi (fy^2 + fx^2)) H F chi."""
+    near = det_lambda_z is not None
     O, U, r, w = _as_inputs(obj, probe, positions, weights)
     Im_all = np.asarray(I_meas).astype(np.float64)
     K, N = r.shape[0], U.shape[-1]
@@ -276,7 +286,15 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
     tf = fresnel_tf(N, lambda_z) if S > 1 else None
     want_pos = "pos" in grads
     want_w = "weights" in grads
+    want_lz = "lambda_z" in grads
+    if want_lz and not near:
+        raise ValueError("the lambda_z gradient belongs to the near-field model")
     any_grad = len(grads) > 0
+    if near:
+        tf_det = fresnel_tf(N, float(det_lambda_z))
+        f = np.fft.fftfreq(N)
+        q2 = f[:, None] ** 2 + f[None, :] ** 2
+        g_lz = 0.0
     gO = np.zeros_like(O)
     gU = np.zeros_like(U)
     gr = np.zeros((K, 2))
@@ -288,14 +306,22 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
         wk = None if w is None else w[k]
         P = probe_for_position(U, wk)
         patches, psis, Psi = _forward_one(O, P, y0, x0, fy, fx, tf)
+        if near:
+            X = Psi                                   # F chi of the last exit wave
+            Psi = ifft2u(tf_det * X)                  # detector-plane wave
         I = np.sum(np.abs(Psi) ** 2, axis=0)          # unshifted incoherent sum
-        Im = uncentre(Im_all[k])
+        Im = Im_all[k] if near else uncentre(Im_all[k])
         l, c = loss_and_factor(I, Im, loss, eps)
         total += float(np.sum(l))
-        I_pred[k] = centre(I)
+        I_pred[k] = I if near else centre(I)
         if not any_grad:
             continue
         gPsi = (2.0 * scale) * c[None] * Psi
+        if near:
+            Gd = fft2u(gPsi)
+            if want_lz:
+                g_lz += float(np.sum(np.real(np.conj(Gd) * (-1j * math.pi * q2) * tf_det * X)))
+            gPsi = np.conj(tf_det) * Gd               # far-field-domain gradient of chi
         g_patch, gwk = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
                                      gO, gU, want_w)
         if want_w:
@@ -314,6 +340,8 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
         out["g_pos"] = gr
     if want_w:
         out["g_weights"] = gw
+    if want_lz:
+        out["g_lambda_z"] = g_lz
     return out
 
 

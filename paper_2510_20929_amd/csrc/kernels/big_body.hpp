@@ -35,6 +35,7 @@ template <int N, int TT>
 struct BigShared {
   float2 tile[Big<N, TT>::LDS];
   double red[2 * (TT / WAVE)];
+  double wred[BIG_MAX_EIG * (TT / WAVE)];
   float wsh[BIG_MAX_EIG];
   double wacc[BIG_MAX_EIG];
 };
@@ -161,6 +162,11 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       if (a.mode == MODE_FORWARD) continue;
     }
 
+    // per-thread partial sums of the weight gradients Re<gP, U_e,m>, reduced once per position
+    const bool want_w = (a.want & WANT_WEIGHTS) && wk != nullptr;
+    double ws[BIG_MAX_EIG];
+#pragma unroll
+    for (int e = 0; e < BIG_MAX_EIG; ++e) ws[e] = 0.0;
     for (int m = 0; m < M; ++m) {
       // inverse column transforms of the scaled far field
       for (int cb = 0; cb < N / RB; ++cb) {
@@ -198,15 +204,13 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             }
           }
         }
-        if ((a.want & WANT_WEIGHTS) && wk != nullptr) {
-          for (int e = 0; e < a.E; ++e) {
-            double s = 0.0;
-            for (int i = tid; i < RB * N; i += T) {
-              const int pix = (rb * RB + i / N) * N + (i % N);
-              s += double(cdotre(tile[(i / N) * RP + (i % N)], a.probe[(size_t(e) * M + m) * NN + pix]));
-            }
-            s = block_sum<T>(s, red);
-            if (tid == 0) wacc[e] += s;
+        if (want_w) {
+          for (int i = tid; i < RB * N; i += T) {
+            const int pix = (rb * RB + i / N) * N + (i % N);
+            const float2 gP = tile[(i / N) * RP + (i % N)];
+#pragma unroll
+            for (int e = 0; e < BIG_MAX_EIG; ++e)
+              if (e < a.E) ws[e] += double(cdotre(gP, a.probe[(size_t(e) * M + m) * NN + pix]));
           }
         }
         __syncthreads();
@@ -254,6 +258,11 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         a.pos_part[2 * k] = v[0];
         a.pos_part[2 * k + 1] = v[1];
       }
+    }
+    if (want_w) {
+      block_sum_n<T, BIG_MAX_EIG>(ws, sh.wred);
+      if (tid == 0)
+        for (int e = 0; e < a.E; ++e) wacc[e] = ws[e];
     }
     __syncthreads();
     if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights && tid < a.E) a.w_part[size_t(k) * a.E + tid] = wacc[tid];
