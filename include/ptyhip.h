@@ -17,7 +17,8 @@
  * Conventions (each is a reading of a point the paper leaves open):
  *   - complex arrays are interleaved (re, im) float32 pairs ("complex64"), row-major;
  *   - the DFT is unitary with kernel exp(-2 pi i k.n / N);
- *   - measured and predicted intensities are DC-centred (fftshift layout);
+ *   - measured and predicted intensities are DC-centred (fftshift layout) in the far field
+ *     and in natural pixel order in the near field;
  *   - a position (y, x) is the frame's top-left corner in object pixels; the integer
  *     part is the floor, the fraction drives bilinear interpolation; the window is
  *     N x N, one row/column wider when the fraction is non-zero or position gradients
@@ -72,8 +73,15 @@ enum {
   PTYHIP_GRAD_WEIGHTS = 8,  /* OPR weight gradient           [K][E] float */
   PTYHIP_ACCUMULATE = 16,   /* add into the outputs (and loss) instead of overwriting */
   PTYHIP_PLAIN = 32,        /* run the per-step kernels instead of the fused kernel */
-  PTYHIP_BATCH_PER_CALL = 64 /* batch only: one non-captured fused call per dataset */
+  PTYHIP_BATCH_PER_CALL = 64, /* batch only: one non-captured fused call per dataset */
+  PTYHIP_GRAD_LAMBDA_Z = 128  /* near field: dL/d(det_lambda_z), device double[1] */
 };
+
+/* propagation to the detector */
+typedef enum {
+  PTYHIP_PROP_FAR = 0, /* far field: unitary 2D DFT, DC-centred detector */
+  PTYHIP_PROP_NEAR = 1 /* near field: Fresnel propagation F^-1 H F, natural pixel order */
+} ptyhip_propagation;
 
 /* bits of the device error latch */
 enum { PTYHIP_FLAG_BOUNDS = 1, PTYHIP_FLAG_NONFINITE = 2 };
@@ -90,6 +98,10 @@ typedef struct {
   float poisson_eps;    /* eps of the Poisson loss, photons (>= 0) */
   float lambda_z;       /* slice spacing times wavelength, px^2 (used when S > 1) */
   double norm_count;    /* K_norm of the 1/(K_norm N^2) normaliser; <= 0: K of the call */
+  int32_t propagation;  /* a ptyhip_propagation value: far- or near-field propagation in the
+                           forward model (Software design, Overview); near needs S == 1, N <= 128 */
+  float det_lambda_z;   /* near field: wavelength times detector distance, px^2; the detector
+                           wave is F^-1(exp(-i pi det_lambda_z (fy^2 + fx^2)) F chi) */
 } ptyhip_desc;
 
 /* Optional implementation choices (the autotuner's search space). Zero = default. */
@@ -134,9 +146,9 @@ ptyhip_status ptyhip_plan_get_info(ptyhip_plan plan, ptyhip_plan_info* info);
 /* Forward model and loss (Eq. (1) / Poisson) for K positions.
  *   obj       [S][H][W] complex      probe   [E][M][N][N] complex
  *   weights   [K][E] float or NULL (NULL requires E == 1 and means w = 1)
- *   positions [K][2] float (y, x)    I_meas  [K][N][N] float, DC-centred
+ *   positions [K][2] float (y, x)    I_meas  [K][N][N] float, DC-centred (near field: natural order)
  *   loss      device double[1] (written, or added to with PTYHIP_ACCUMULATE)
- *   I_pred    [K][N][N] float DC-centred, or NULL */
+ *   I_pred    [K][N][N] float, same layout as I_meas, or NULL */
 ptyhip_status ptyhip_forward(ptyhip_plan plan, void* stream, int32_t K, const float* obj, const float* probe,
                              const float* weights, const float* positions, const float* I_meas, double* loss,
                              float* I_pred);
@@ -149,6 +161,15 @@ ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, 
                                      const float* probe, const float* weights, const float* positions,
                                      const float* I_meas, double* loss, float* I_pred, float* g_obj,
                                      float* g_probe, float* g_pos, float* g_weights);
+
+/* As ptyhip_forward_adjoint, plus the near-field gradient with respect to det_lambda_z
+ * (PTYHIP_GRAD_LAMBDA_Z; device double[1], overwritten or accumulated like the loss):
+ * dL/d(lz) = sum_k,m Re sum_f conj(F g_Psi) (-i pi (fy^2 + fx^2)) H F chi, by the chain
+ * rule through the propagator. The flag requires a near-field plan. */
+ptyhip_status ptyhip_forward_adjoint_ex(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
+                                        const float* probe, const float* weights, const float* positions,
+                                        const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                        float* g_probe, float* g_pos, float* g_weights, double* g_lambda_z);
 
 /* The linear map (object, probe) -> far-field waves Psi [K][M][N][N] (unshifted),
  * and its adjoint (for the identity <A x, y> = <x, A^H y>): apply_AH takes Y [K][M][N][N]

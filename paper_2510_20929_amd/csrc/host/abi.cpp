@@ -98,12 +98,18 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
     if ((st = dalloc(p, &p->tf, NN)) != PTYHIP_OK) return st;
     if (hipMemcpy(p->tf, h.data(), NN * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return PTYHIP_EHIP;
   }
+  if (d.propagation == PTYHIP_PROP_NEAR) {
+    std::vector<float2> h = fresnel(N, double(d.det_lambda_z));
+    if ((st = dalloc(p, &p->tfd, NN)) != PTYHIP_OK) return st;
+    if (hipMemcpy(p->tfd, h.data(), NN * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) return PTYHIP_EHIP;
+  }
   if ((st = dalloc(p, &p->flags, 1)) != PTYHIP_OK) return st;
   if (hipMemset(p->flags, 0, sizeof(uint32_t)) != hipSuccess) return PTYHIP_EHIP;
   const size_t kk = size_t(std::max(maxK, 1));
   if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
+  if (d.propagation == PTYHIP_PROP_NEAR && (st = dalloc(p, &p->lz_part, kk)) != PTYHIP_OK) return st;
   p->copies = 1;
   p->probe_elems = size_t(E) * M * NN;
   if ((st = dalloc(p, &p->gprobe_part, p->probe_elems)) != PTYHIP_OK) return st;
@@ -114,7 +120,8 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   const int recompute = p->tune.recompute ? 1 : 0;
   if (p->on_chip) {
     p->threads = fused_small_threads(N, p->tune.variant);
-    p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off, p->tune.variant);
+    p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off, p->tune.variant,
+                                                  d.propagation == PTYHIP_PROP_NEAR);
   } else {
     p->threads = 256;
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
@@ -178,6 +185,11 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
   if (!std::isfinite(d->lambda_z)) return PTYHIP_ENONFINITE;
   if (!std::isfinite(d->norm_count)) return PTYHIP_ENONFINITE;
   if (d->n_slices > 1 && d->frame > 128) return PTYHIP_EUNSUPPORTED;
+  if (d->propagation != PTYHIP_PROP_FAR && d->propagation != PTYHIP_PROP_NEAR) return PTYHIP_EINVAL;
+  if (d->propagation == PTYHIP_PROP_NEAR) {
+    if (!std::isfinite(d->det_lambda_z)) return PTYHIP_ENONFINITE;
+    if (d->n_slices > 1 || d->frame > 128) return PTYHIP_EUNSUPPORTED;
+  }
   return PTYHIP_OK;
 }
 
@@ -208,6 +220,8 @@ CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj,
   a.flags = p->flags;
   a.tw = p->tw;
   a.tf = p->tf;
+  a.tfd = p->tfd;
+  a.near = d.propagation == PTYHIP_PROP_NEAR ? 1 : 0;
   a.scratch = p->scratch;
   a.scratch_stride = p->scratch_stride;
   a.pacc_off = p->pacc_off;
@@ -245,6 +259,7 @@ static CallArgs chunk_args(const CallArgs& a, int k0, int n, int N, int E, int M
   c.loss_part = a.loss_part + k0;
   c.pos_part = a.pos_part ? a.pos_part + size_t(2) * k0 : nullptr;
   c.w_part = a.w_part ? a.w_part + size_t(E) * k0 : nullptr;
+  c.lz_part = a.lz_part ? a.lz_part + k0 : nullptr;
   c.zero_acc = k0 == 0 ? 1 : 0;
   return c;
 }
@@ -327,7 +342,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
 ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
                                    const float* probe, const float* weights, const float* positions,
                                    const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,
-                                   float* g_pos, float* g_weights, bool forward_only) {
+                                   float* g_pos, float* g_weights, double* g_lz, bool forward_only) {
   if (p == nullptr) return PTYHIP_EINVAL;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   const ptyhip_desc& d = p->d;
@@ -338,18 +353,26 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   const bool want_probe = !forward_only && (flags & PTYHIP_GRAD_PROBE);
   const bool want_pos = !forward_only && (flags & PTYHIP_GRAD_POS);
   const bool want_w = !forward_only && (flags & PTYHIP_GRAD_WEIGHTS);
+  const bool near = d.propagation == PTYHIP_PROP_NEAR;
+  const bool want_lz = !forward_only && (flags & PTYHIP_GRAD_LAMBDA_Z);
+  if (want_lz && (!near || !g_lz)) return PTYHIP_EINVAL;
+  if (near && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;
   if (want_pos && K > 0 && !g_pos) return PTYHIP_EINVAL;
   if (want_w && K > 0 && (!g_weights || !weights)) return PTYHIP_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
   const bool acc = (flags & PTYHIP_ACCUMULATE) != 0;
-  const bool any_grad = want_obj || want_probe || want_pos || want_w;
+  const bool any_grad = want_obj || want_probe || want_pos || want_w || want_lz;
   const int mode = (forward_only || !any_grad) ? MODE_FORWARD : MODE_FWD_ADJ;
   const bool plain = (flags & PTYHIP_PLAIN) != 0;
   const bool fused = uses_fused(p, plain);
   CallArgs a = make_args(p, K, mode, fused, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
                          want_obj ? g_obj : nullptr, want_probe, want_pos, want_w);
+  if (want_lz) {
+    a.lz_part = p->lz_part;
+    a.want |= WANT_LZ;
+  }
   ptyhip_status s = run_call(p, a, plain, acc, want_obj ? g_obj : nullptr, want_probe ? g_probe : nullptr, st);
   if (s != PTYHIP_OK) return s;
   FinalArgs f;
@@ -362,6 +385,8 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   f.g_w = want_w ? g_weights : nullptr;
   f.gprobe_part = p->gprobe_part;
   f.g_probe = (want_probe && !fused) ? reinterpret_cast<float2*>(g_probe) : nullptr;
+  f.lz_part = want_lz ? p->lz_part : nullptr;
+  f.g_lz = want_lz ? g_lz : nullptr;
   f.copies = 1;
   f.probe_elems = p->probe_elems;
   f.K = K;
@@ -444,15 +469,26 @@ ptyhip_status ptyhip_forward(ptyhip_plan plan, void* stream, int32_t K, const fl
                              const float* weights, const float* positions, const float* I_meas, double* loss,
                              float* I_pred) {
   return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K, 0, obj, probe,
-                              weights, positions, I_meas, loss, I_pred, nullptr, nullptr, nullptr, nullptr, true);
+                              weights, positions, I_meas, loss, I_pred, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              true);
 }
 
 ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
                                      const float* probe, const float* weights, const float* positions,
                                      const float* I_meas, double* loss, float* I_pred, float* g_obj,
                                      float* g_probe, float* g_pos, float* g_weights) {
+  return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K,
+                              flags & ~uint32_t(PTYHIP_GRAD_LAMBDA_Z), obj, probe, weights, positions, I_meas, loss,
+                              I_pred, g_obj, g_probe, g_pos, g_weights, nullptr, false);
+}
+
+ptyhip_status ptyhip_forward_adjoint_ex(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
+                                        const float* probe, const float* weights, const float* positions,
+                                        const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                        float* g_probe, float* g_pos, float* g_weights, double* g_lambda_z) {
   return call_forward_adjoint(reinterpret_cast<Plan*>(plan), static_cast<hipStream_t>(stream), K, flags, obj, probe,
-                              weights, positions, I_meas, loss, I_pred, g_obj, g_probe, g_pos, g_weights, false);
+                              weights, positions, I_meas, loss, I_pred, g_obj, g_probe, g_pos, g_weights, g_lambda_z,
+                              false);
 }
 
 ptyhip_status ptyhip_illumination(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* probe,
@@ -552,6 +588,7 @@ ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const fl
                              const float* weights, const float* positions, float* Psi) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
+  if (p->d.propagation == PTYHIP_PROP_NEAR) return PTYHIP_EUNSUPPORTED;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   if (!obj || !probe || (K > 0 && (!positions || !Psi))) return PTYHIP_EINVAL;
   if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
@@ -568,6 +605,7 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
                               float* g_probe) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
+  if (p->d.propagation == PTYHIP_PROP_NEAR) return PTYHIP_EUNSUPPORTED;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   if (!obj || !probe || (K > 0 && (!Y || !positions))) return PTYHIP_EINVAL;
   if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;

@@ -62,7 +62,7 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     ptyhip_status s = validate_desc(&descs[i]);
     if (s != PTYHIP_OK) return s;
     const int N = descs[i].frame;
-    if (N < 64 || descs[i].n_slices != 1) return PTYHIP_EUNSUPPORTED;
+    if (N < 64 || descs[i].n_slices != 1 || descs[i].propagation != PTYHIP_PROP_FAR) return PTYHIP_EUNSUPPORTED;
     if (K[i] < 0) return PTYHIP_EBOUNDS;
   }
   auto* b = new (std::nothrow) ptyhip_batch_s();
@@ -197,7 +197,7 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
     for (int i = 0; i < b->n; ++i) {
       const Bound& d = b->bound[i];
       ptyhip_status s = call_forward_adjoint(b->plans[i], st, b->K[i], f, d.obj, d.probe, d.weights, d.pos, d.imeas,
-                                             d.loss, nullptr, d.g_obj, d.g_probe, d.g_pos, d.g_w, false);
+                                             d.loss, nullptr, d.g_obj, d.g_probe, d.g_pos, d.g_w, nullptr, false);
       if (s != PTYHIP_OK) return s;
     }
     return PTYHIP_OK;

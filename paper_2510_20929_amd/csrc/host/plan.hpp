@@ -25,6 +25,8 @@ struct Plan {
   // tables and per-call partials
   float2* tw = nullptr;
   float2* tf = nullptr;
+  float2* tfd = nullptr;      // near field: transfer function to the detector
+  double* lz_part = nullptr;  // near field: per-position dL/d(det_lambda_z)
   uint32_t* flags = nullptr;
   double* loss_part = nullptr;
   double* pos_part = nullptr;
@@ -77,6 +79,6 @@ CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj,
 ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
                                    const float* probe, const float* weights, const float* positions,
                                    const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,
-                                   float* g_pos, float* g_weights, bool forward_only);
+                                   float* g_pos, float* g_weights, double* g_lz, bool forward_only);
 
 }  // namespace ptyhip

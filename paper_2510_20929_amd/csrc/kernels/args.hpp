@@ -14,6 +14,7 @@ enum WantBits : int {
   WANT_POS = 4,
   WANT_WEIGHTS = 8,
   WANT_IPRED = 16,
+  WANT_LZ = 32,
 };
 
 struct CallArgs {
@@ -34,10 +35,12 @@ struct CallArgs {
   double* loss_part;      // [K] per-position loss (already normalised)
   double* pos_part;       // [K][2]
   double* w_part;         // [K][E]
+  double* lz_part;        // near field: [K] dL/d(lambda z_det) per position
   uint32_t* flags;        // device error latch
   // tables and workspace
   const float2* tw;       // W_N^j, j in [0, N)
   const float2* tf;       // Fresnel transfer function [N][N] (unshifted), S > 1
+  const float2* tfd;      // near field: transfer function to the detector [N][N] (unshifted)
   float2* scratch;        // per-workgroup scratch base
   size_t scratch_stride;  // float2 elements per workgroup
   size_t pacc_off;        // offset of the probe-gradient accumulator in a workgroup's scratch
@@ -51,6 +54,7 @@ struct CallArgs {
   int want;               // WantBits
   int mode;               // CallMode
   int recompute;          // multislice: recompute incident waves instead of storing them
+  int near;               // 1: near-field detector (Fresnel propagation, natural pixel order)
 };
 
 }  // namespace ptyhip

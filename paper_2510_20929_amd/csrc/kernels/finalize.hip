@@ -34,6 +34,8 @@ __global__ void finalize_elems_kernel(FinalArgs f) {
 
 hipError_t launch_finalize(const FinalArgs& f, hipStream_t st) {
   if (f.loss) hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, f.loss_part, f.K, f.loss, f.accumulate);
+  if (f.g_lz && f.lz_part)
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, f.lz_part, f.K, f.g_lz, f.accumulate);
   size_t n = 0;
   if (f.g_pos) n = size_t(f.K) * 2;
   if (f.g_w && size_t(f.K) * f.E > n) n = size_t(f.K) * f.E;

@@ -11,6 +11,12 @@ __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   small_body<N, T, LOSS, RV>(a, sh, blockIdx.x, gridDim.x);
 }
 
+template <int N, int T, int LOSS>
+__global__ __launch_bounds__(T) void fused_small_near_kernel(CallArgs a) {
+  __shared__ SmallShared<N, T> sh;
+  small_body_near<N, T, LOSS>(a, sh, blockIdx.x, gridDim.x);
+}
+
 // ----------------------------------------------------------------------------- multislice
 // Scratch per workgroup (element i of thread t at i*T + t):
 //   patches [S][NN], patch gradients [S][NN], incident waves [M][S][NN] (unless
@@ -244,6 +250,11 @@ __global__ __launch_bounds__(256) void probe_reduce_kernel(const float2* __restr
 template <int N, int T, bool RV = false>
 static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   const bool ms = a.S > 1;
+  if (a.near) {
+    if (a.loss == 0) hipLaunchKernelGGL((fused_small_near_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_near_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.loss == 0) {
     if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
     else hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV>), dim3(grid), dim3(T), 0, st, a);
@@ -277,10 +288,12 @@ int fused_small_threads(int N, int variant) {
 }
 
 // per-workgroup scratch (float2 elements) and the offset of the probe accumulator
-size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant) {
+size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant,
+                                 bool near) {
   const size_t fr = size_t(N) * N;
   size_t base;
   if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  else if (near) base = fr * (2 + size_t(M));
   else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
   else base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
   *pacc_off = base;

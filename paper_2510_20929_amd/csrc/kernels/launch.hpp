@@ -29,6 +29,8 @@ struct FinalArgs {
   float* g_w;               // [K][E] or nullptr
   const float2* gprobe_part;  // [copies][E*M*N*N] or nullptr
   float2* g_probe;          // [E*M*N*N] or nullptr
+  const double* lz_part;    // [K] or nullptr
+  double* g_lz;             // device scalar or nullptr
   int copies;
   size_t probe_elems;
   int K, E;
@@ -66,7 +68,8 @@ hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inv
 hipError_t run_plain_chunk(PlainArgs b, hipStream_t st);
 
 int fused_small_threads(int N, int variant);
-size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant);
+size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant,
+                                 bool near = false);
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
 hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
                                      int accumulate, hipStream_t st);

@@ -112,19 +112,22 @@ __device__ __forceinline__ void skip_position(const CallArgs& a, int k, const Po
 
 // Loss of one position from the incoherent sum held in layout D; on return Iacc holds
 // dl/dI. Returns false if the position's loss is not finite (then it is skipped).
-template <int N, int T, int LOSS>
+// NAT: the intensity is held in layout A and the detector is in natural pixel order
+// (near field); otherwise layout D and a DC-centred detector.
+template <int N, int T, int LOSS, bool NAT = false>
 __device__ __forceinline__ bool position_loss(const CallArgs& a, int k, float (&Iacc)[Frame2D<N, T>::E],
                                               double* red) {
   using C = SmallCtx<N, T>;
   const float* im = a.imeas + size_t(k) * C::NN;
   const int t = opaque_tid();
+  auto idx = [&](int i) { return NAT ? C::a_pix(t, i) : C::d_centred(t, i); };
   float imv[C::E];
 #pragma unroll
-  for (int i = 0; i < C::E; ++i) imv[i] = __builtin_nontemporal_load(im + C::d_centred(t, i));
+  for (int i = 0; i < C::E; ++i) imv[i] = __builtin_nontemporal_load(im + idx(i));
   if (a.ipred) {
     float* ip = a.ipred + size_t(k) * C::NN;
 #pragma unroll
-    for (int i = 0; i < C::E; ++i) __builtin_nontemporal_store(Iacc[i], ip + C::d_centred(t, i));
+    for (int i = 0; i < C::E; ++i) __builtin_nontemporal_store(Iacc[i], ip + idx(i));
   }
   double lsum = 0.0;
 #pragma unroll
@@ -454,6 +457,157 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
       probe_gradients<N, T, (RV ? 4 : E)>(a, m, wk, v, sb, pacc_b, red, wacc);
     }
 
+    __syncthreads();
+    double gy = 0.0, gx = 0.0;
+    window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);
+    finish_position<N, T>(a, k, gy, gx, red, wacc);
+  }
+}
+
+// Near-field detector: Psi = F^-1(H F chi) with the detector transfer function H, the
+// intensity and the loss in layout A (natural pixel order). Per mode the far field
+// X = F chi is kept in the workgroup's scratch; the adjoint rebuilds Psi from it (one
+// transform), transforms g_Psi (one), takes the det_lambda_z gradient
+// Re sum_f conj(F g_Psi) (-i pi q^2) H X, and brings conj(H) F g_Psi back (one).
+// Scratch: patch [NN], patch-gradient accumulator [NN], X of every mode [M][NN], probe
+// accumulator.
+template <int N, int T, int LOSS>
+__device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N, T>& sh, int wg, int nwg) {
+  using F = Frame2D<N, T>;
+  using C = SmallCtx<N, T>;
+  constexpr int E = C::E;
+  float2* lds = sh.lds;
+  float2* tws = sh.tws;
+  double* red = sh.red;
+  float* wsh = sh.wsh;
+  double* wacc = sh.wacc;
+  const float inv_n = 1.f / float(N);
+  const bool adj = a.mode == MODE_FWD_ADJ;
+  const bool want_pos = (a.want & WANT_POS) && adj;
+  const bool want_lz = (a.want & WANT_LZ) && adj && a.lz_part != nullptr;
+  for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
+  float2* scr = a.scratch + size_t(wg) * a.scratch_stride;
+  const BufFrame sb(scr, uint32_t(a.scratch_stride * sizeof(float2)));
+  constexpr int GACC_B = C::NN * 8;
+  constexpr int X_B = 2 * C::NN * 8;
+  const int pacc_b = int(a.pacc_off * sizeof(float2));
+  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  // frequency of element i in layout D, cycles per pixel, squared
+  auto q2 = [&](int t, int i) {
+    const int l = i / C::N2, ii = i % C::N2;
+    const int ky = F::d_ky(t, l, ii), kx = F::d_kx(t, l);
+    const float fy = float(ky < N / 2 ? ky : ky - N) * inv_n, fx = float(kx < N / 2 ? kx : kx - N) * inv_n;
+    return fy * fy + fx * fx;
+  };
+
+  for (int k = wg; k < a.K; k += nwg) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) {
+      skip_position<N, T>(a, k, p);
+      if (threadIdx.x == 0 && a.lz_part) a.lz_part[k] = 0.0;
+      continue;
+    }
+    __syncthreads();
+    if (a.weights && int(threadIdx.x) < a.E) wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
+    if (threadIdx.x < MAX_EIG) wacc[threadIdx.x] = 0.0;
+    __syncthreads();
+    const float* wk = a.weights ? wsh : nullptr;
+    {
+      const int t = opaque_tid();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = i / C::N2, j = i % C::N2;
+        sb.st(bilinear(a.obj, a.W, p, F::a_y(t, l), F::a_x(t, l, j)), t * 8, i * T * 8);
+      }
+    }
+    float2 v[E];
+    float cf[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) cf[i] = 0.f;
+    for (int m = 0; m < a.M; ++m) {
+      {
+        const int t = opaque_tid();
+        for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) { v[i] = cmul(P, sb.ld(t * 8, i * T * 8)); });
+      }
+      F::forward(v, lds, tws, inv_n);
+      {
+        const int t = opaque_tid();
+        const int xb = X_B + m * C::NN * 8;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          if (adj) sb.st(v[i], t * 8, xb + i * T * 8);
+          v[i] = cmul(v[i], a.tfd[C::d_freq(t, i)]);
+        }
+      }
+      F::inverse(v, lds, tws, inv_n);
+#pragma unroll
+      for (int i = 0; i < E; ++i) cf[i] += cabs2(v[i]);
+    }
+    if (!position_loss<N, T, LOSS, true>(a, k, cf, red)) {
+      if (threadIdx.x == 0 && a.lz_part) a.lz_part[k] = 0.0;
+      continue;
+    }
+    if (!adj) continue;
+
+    double lz = 0.0;
+    for (int mm = 0; mm < a.M; ++mm) {
+      const int m = a.M - 1 - mm;
+      const int xb = X_B + m * C::NN * 8;
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = cmul(sb.ld(t * 8, xb + i * T * 8), a.tfd[C::d_freq(t, i)]);
+      }
+      F::inverse(v, lds, tws, inv_n);  // detector wave Psi (layout A)
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = cscale(v[i], a.gscale * cf[i]);
+      F::forward(v, lds, tws, inv_n);  // F g_Psi (layout D)
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const float2 h = a.tfd[C::d_freq(t, i)];
+          if (want_lz) {
+            const float2 z = cmul(h, sb.ld(t * 8, xb + i * T * 8));
+            lz += double(3.14159265358979323846f * q2(t, i) * (v[i].x * z.y - v[i].y * z.x));
+          }
+          v[i] = cmulc(h, v[i]);
+        }
+      }
+      F::inverse(v, lds, tws, inv_n);  // gradient of the exit wave (layout A)
+      const bool last = mm == a.M - 1;
+      __syncthreads();
+      {
+        const int t = opaque_tid();
+        auto pass = [&](auto first_c, auto last_c) {
+          constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
+          for_probe<N, T>(a, wk, m, t, [&](int i, float2 P) {
+            float2 g = cmulc(P, v[i]);
+            if constexpr (!FIRST) g = cadd(g, sb.ld(t * 8, GACC_B + i * T * 8));
+            if constexpr (!LAST) sb.st(g, t * 8, GACC_B + i * T * 8);
+            if constexpr (LAST) {
+              const int pix = C::a_pix(t, i);
+              lds[(pix / N) * F::P + (pix % N)] = g;
+            }
+            v[i] = cmulc(sb.ld(t * 8, i * T * 8), v[i]);
+          });
+        };
+        using T0 = std::false_type;
+        using T1 = std::true_type;
+        if (mm == 0) {
+          if (last) pass(T1{}, T1{});
+          else pass(T1{}, T0{});
+        } else {
+          if (last) pass(T0{}, T1{});
+          else pass(T0{}, T0{});
+        }
+      }
+      probe_gradients<N, T>(a, m, wk, v, sb, pacc_b, red, wacc);
+    }
+    if (want_lz) {
+      const double tot = block_sum<T>(lz, red);
+      if (threadIdx.x == 0) a.lz_part[k] = tot;
+    }
     __syncthreads();
     double gy = 0.0, gx = 0.0;
     window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);

@@ -23,6 +23,8 @@ GRAD_POS = 4
 GRAD_WEIGHTS = 8
 ACCUMULATE = 16
 PLAIN = 32
+GRAD_LAMBDA_Z = 128
+PROP_FAR, PROP_NEAR = 0, 1
 FLAG_BOUNDS = 1
 FLAG_NONFINITE = 2
 
@@ -31,7 +33,8 @@ STATUS = {0: "PTYHIP_OK", 1: "PTYHIP_EINVAL", 2: "PTYHIP_ESHAPE", 3: "PTYHIP_EBO
 
 EXPORTED = [
     "ptyhip_status_str", "ptyhip_version", "ptyhip_desc_validate", "ptyhip_plan_create", "ptyhip_plan_create_ex",
-    "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint", "ptyhip_apply_A",
+    "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint",
+    "ptyhip_forward_adjoint_ex", "ptyhip_apply_A",
     "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients",
     "ptyhip_orthogonalize_modes", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
     "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
@@ -43,7 +46,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("frame", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("n_eig", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("obj_h", ctypes.c_int32), ("obj_w", ctypes.c_int32),
                 ("loss", ctypes.c_int32), ("poisson_eps", ctypes.c_float), ("lambda_z", ctypes.c_float),
-                ("norm_count", ctypes.c_double)]
+                ("norm_count", ctypes.c_double), ("propagation", ctypes.c_int32), ("det_lambda_z", ctypes.c_float)]
 
 
 class Tune(ctypes.Structure):
@@ -118,10 +121,13 @@ def _check(status: int, what: str):
 
 
 def make_desc(frame, n_modes=1, n_eig=1, n_slices=1, obj_h=0, obj_w=0, loss="amplitude", poisson_eps=1e-3,
-              lambda_z=0.0, norm_count=0.0) -> Desc:
+              lambda_z=0.0, norm_count=0.0, det_lambda_z=None) -> Desc:
+    """det_lambda_z=None: far-field detector; a number: near-field (Fresnel) detector."""
     lc = {"amplitude": LOSS_AMPLITUDE, "poisson": LOSS_POISSON}.get(loss, loss)
+    near = det_lambda_z is not None
     return Desc(int(frame), int(n_modes), int(n_eig), int(n_slices), int(obj_h), int(obj_w), int(lc),
-                float(poisson_eps), float(lambda_z), float(norm_count))
+                float(poisson_eps), float(lambda_z), float(norm_count), PROP_NEAR if near else PROP_FAR,
+                float(det_lambda_z) if near else 0.0)
 
 
 def ptyhip_desc_validate(desc: Desc) -> int:
@@ -157,8 +163,10 @@ class Plan:
     """A ptyhip plan for one problem shape (owns the library workspace)."""
 
     def __init__(self, frame, n_modes=1, n_eig=1, n_slices=1, obj_h=0, obj_w=0, loss="amplitude",
-                 poisson_eps=1e-3, lambda_z=0.0, norm_count=0.0, max_positions=1, tune: Optional[dict] = None):
-        self.desc = make_desc(frame, n_modes, n_eig, n_slices, obj_h, obj_w, loss, poisson_eps, lambda_z, norm_count)
+                 poisson_eps=1e-3, lambda_z=0.0, norm_count=0.0, max_positions=1, tune: Optional[dict] = None,
+                 det_lambda_z=None):
+        self.desc = make_desc(frame, n_modes, n_eig, n_slices, obj_h, obj_w, loss, poisson_eps, lambda_z, norm_count,
+                              det_lambda_z)
         self.max_positions = int(max_positions)
         h = ctypes.c_void_p()
         if tune:
@@ -177,7 +185,7 @@ class Plan:
     def for_problem(cls, prob, max_positions=None, norm_count=0.0, tune=None):
         """Plan sized for a synthetic ``synth.Problem``-like object."""
         return cls(prob.N, prob.M, prob.E, prob.S, prob.H, prob.W, prob.loss, prob.eps, prob.lambda_z, norm_count,
-                   max_positions or prob.K, tune)
+                   max_positions or prob.K, tune, getattr(prob, "det_lambda_z", None))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -243,6 +251,10 @@ class Plan:
             flags |= GRAD_WEIGHTS
             if "g_weights" not in out:
                 out["g_weights"] = torch.zeros((K, self.E), dtype=torch.float32, device=dev)
+        if "lambda_z" in grads:
+            flags |= GRAD_LAMBDA_Z
+            if "g_lambda_z" not in out:
+                out["g_lambda_z"] = torch.zeros(1, dtype=torch.float64, device=dev)
         if accumulate:
             flags |= ACCUMULATE
         if plain:
@@ -250,10 +262,10 @@ class Plan:
         if I_pred is not None:
             _need(I_pred, "I_pred", torch.float32, (K, self.N, self.N))
             out["I_pred"] = I_pred
-        st = _lib().ptyhip_forward_adjoint(
+        st = _lib().ptyhip_forward_adjoint_ex(
             self._h, _stream(stream), K, flags, _ptr(obj), _ptr(probe), _ptr(weights), _ptr(positions),
             _ptr(I_meas), _ptr(out["loss"]), _ptr(I_pred), _ptr(out.get("g_obj")), _ptr(out.get("g_probe")),
-            _ptr(out.get("g_pos")), _ptr(out.get("g_weights")))
+            _ptr(out.get("g_pos")), _ptr(out.get("g_weights")), _ptr(out.get("g_lambda_z")))
         _check(st, "ptyhip_forward_adjoint")
         return out
 

@@ -39,6 +39,7 @@ class Problem:
     eps: float = 1.0e-3             # Poisson regulariser, photons
     lambda_z: float = 0.0           # slice-to-slice Fresnel product, px^2
     grads: Tuple[str, ...] = ("obj", "probe")
+    det_lambda_z: Optional[float] = None  # near-field detector (Fresnel), or None: far field
 
     @property
     def N(self) -> int:

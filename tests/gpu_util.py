@@ -44,7 +44,8 @@ def rel_l2(got, ref) -> float:
 def measured(truth, seed: int):
     """Noisy measured intensities of a truth problem (clean intensities from the oracle)."""
     _, I_clean = oracle.forward(truth.obj, truth.probe, truth.positions, np.zeros((truth.K, truth.N, truth.N)),
-                                weights=truth.weights, lambda_z=truth.lambda_z)
+                                weights=truth.weights, lambda_z=truth.lambda_z,
+                                det_lambda_z=getattr(truth, "det_lambda_z", None))
     return W.poisson_counts(I_clean, seed)
 
 
@@ -57,7 +58,7 @@ def case(config: int, seed: int = 5, **kw):
 def run_oracle(prob, I_meas, grads, norm_count=None):
     return oracle.forward_adjoint(prob.obj, prob.probe, prob.positions, I_meas, weights=prob.weights,
                                   loss=prob.loss, eps=prob.eps, lambda_z=prob.lambda_z, norm_count=norm_count,
-                                  grads=grads)
+                                  grads=grads, det_lambda_z=getattr(prob, "det_lambda_z", None))
 
 
 def run_gpu(plan, prob, I_meas, grads, plain=False, want_ipred=True):
@@ -77,7 +78,7 @@ def compare(got, ref, grads, tag=""):
     errs = {"loss": abs(got["loss"] - ref["loss"]) / max(abs(ref["loss"]), 1e-300)}
     if "I_pred" in got:
         errs["I_pred"] = rel_l2(got["I_pred"], ref["I_pred"])
-    names = {"obj": "g_obj", "probe": "g_probe", "pos": "g_pos", "weights": "g_weights"}
+    names = {"obj": "g_obj", "probe": "g_probe", "pos": "g_pos", "weights": "g_weights", "lambda_z": "g_lambda_z"}
     for g in grads:
         errs[names[g]] = rel_l2(got[names[g]], ref[names[g]])
     print(f"{tag} rel errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
@@ -87,7 +88,7 @@ def compare(got, ref, grads, tag=""):
     return errs
 
 
-def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=None):
+def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=None, det_lambda_z=None):
     """Small generic problem (random smooth object, random smooth probes, random
     sub-pixel positions) for shapes no config covers."""
     rng = np.random.default_rng(seed)
@@ -102,6 +103,6 @@ def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=Non
     elif weights == "amp":
         w = rng.uniform(0.85, 1.15, size=(K, E))
     truth = W.Problem("custom", obj.astype(np.complex64), probe.astype(np.complex64), pos.astype(np.float32),
-                      None if w is None else w.astype(np.float32), loss, lambda_z=lz)
+                      None if w is None else w.astype(np.float32), loss, lambda_z=lz, det_lambda_z=det_lambda_z)
     start = W.perturb(truth, seed + 1)
     return start, measured(truth, seed + 2)

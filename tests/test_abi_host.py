@@ -39,10 +39,22 @@ def test_exports_every_declared_symbol():
     (dict(frame=64, obj_h=200, obj_w=200, poisson_eps=float("nan")), 4),
     (dict(frame=64, obj_h=200, obj_w=200, poisson_eps=-1.0), 4),
     (dict(frame=256, n_slices=2, obj_h=600, obj_w=600), 7),
+    (dict(frame=128, obj_h=300, obj_w=300, det_lambda_z=40.0), 0),            # near field
+    (dict(frame=128, obj_h=300, obj_w=300, det_lambda_z=0.0), 0),
+    (dict(frame=256, obj_h=600, obj_w=600, det_lambda_z=40.0), 7),            # near field needs N <= 128
+    (dict(frame=64, n_slices=2, obj_h=200, obj_w=200, det_lambda_z=40.0), 7),  # and one slice
+    (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=float("inf")), 4),
 ])
 def test_desc_validate(kw, status):
     mod = _lib()
     assert mod.ptyhip_desc_validate(mod.make_desc(**kw)) == status
+
+
+def test_desc_rejects_unknown_propagation():
+    mod = _lib()
+    d = mod.make_desc(frame=64, obj_h=200, obj_w=200)
+    d.propagation = 2
+    assert mod.ptyhip_desc_validate(d) == 1
 
 
 def test_status_strings_and_version():
