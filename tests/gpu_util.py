@@ -106,3 +106,74 @@ def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=Non
                       None if w is None else w.astype(np.float32), loss, lambda_z=lz, det_lambda_z=det_lambda_z)
     start = W.perturb(truth, seed + 1)
     return start, measured(truth, seed + 2)
+
+
+def _oracle_clean_chunk(args):
+    """Worker: the oracle's clean intensities of one chunk of positions (runs in a spawned
+    process that never touches the GPU)."""
+    obj, probe, pos, weights, lambda_z, det_lambda_z = args
+    return oracle.forward(obj, probe, pos, np.zeros((pos.shape[0], probe.shape[-1], probe.shape[-1])),
+                          weights=weights, lambda_z=lambda_z, det_lambda_z=det_lambda_z)[1].astype(np.float32)
+
+
+def measured_many(truths, seeds, workers: int = 16, noise: bool = True):
+    """``measured`` for full-size workloads: the oracle's clean intensities computed in
+    parallel over chunks of positions (spawned CPU processes that never touch the GPU),
+    then Poisson noise with each problem's seed."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n = max(1, min(workers, os.cpu_count() or 1))
+    jobs, owner = [], []
+    for t_i, truth in enumerate(truths):
+        pieces = max(1, min(n, truth.K // 8))
+        bounds = np.linspace(0, truth.K, pieces + 1).astype(int)
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            w = None if truth.weights is None else truth.weights[a:b]
+            jobs.append((truth.obj, truth.probe, truth.positions[a:b], w, truth.lambda_z,
+                         getattr(truth, "det_lambda_z", None)))
+            owner.append(t_i)
+    import time
+    t0 = time.time()
+    parts = [None] * len(jobs)
+    with cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn")) as ex:
+        futs = {ex.submit(_oracle_clean_chunk, j): i for i, j in enumerate(jobs)}
+        for done, f in enumerate(cf.as_completed(futs), 1):
+            parts[futs[f]] = f.result()
+            if done % max(1, len(jobs) // 10) == 0 or done == len(jobs):
+                print(f"oracle intensities: {done}/{len(jobs)} chunks, {time.time() - t0:.0f} s", flush=True)
+    out = []
+    for t_i, seed in enumerate(seeds):
+        I = np.concatenate([p for p, o in zip(parts, owner) if o == t_i], axis=0)
+        out.append(W.poisson_counts(I, seed) if noise else I)
+    return out
+
+
+def measured_parallel(truth, seed: int, workers: int = 16):
+    return measured_many([truth], [seed], workers)[0]
+
+
+def measured_sparse(truths, needs, seeds, workers: int = 16):
+    """Measured intensities for full-size launches whose outputs are checked only at some
+    positions: the oracle's clean intensities at the positions in ``needs[i]`` (every
+    output that is compared depends only on those), re-used cyclically for the other
+    positions, then Poisson noise. Every position thus gets a diffraction pattern of
+    the workload's own statistics without running the oracle over all of them."""
+    subs = [t.subset(np.asarray(n)) for t, n in zip(truths, needs)]
+    clean = measured_many(subs, [0] * len(subs), workers=workers, noise=False)
+    out = []
+    for t, n, c, seed in zip(truths, needs, clean, seeds):
+        n = np.asarray(n)
+        full = np.empty((t.K, t.N, t.N), dtype=np.float32)
+        full[np.arange(t.K)] = c[np.arange(t.K) % len(n)]
+        full[n] = c
+        out.append(W.poisson_counts(full, seed))
+    return out
+
+
+def covering(prob, ty: int, tx: int, size: int):
+    """Indices of the positions whose (N+1)^2 window touches the tile [ty, ty+size) x [tx, tx+size)."""
+    y0 = np.floor(prob.positions[:, 0]).astype(int)
+    x0 = np.floor(prob.positions[:, 1]).astype(int)
+    N = prob.N
+    hit = (y0 <= ty + size - 1) & (y0 + N >= ty) & (x0 <= tx + size - 1) & (x0 + N >= tx)
+    return np.nonzero(hit)[0]
