@@ -108,7 +108,8 @@ typedef struct {
 typedef struct {
   int32_t variant;      /* on-chip fused kernel (64^2, 128^2): 0 = 512 threads, patch in scratch;
                            1 = 1024 (128^2) / 256 (64^2) threads; 2 = 512 threads, patch and
-                           patch gradient in registers; 3 = as 2 with 1024 / 256 threads */
+                           patch gradient in registers; 3 = as 2 with 1024 / 256 threads;
+                           4 = as 3 with the patch gradient in scratch */
   int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
   int32_t recompute;    /* 1 = recompute (multislice: incident waves; several modes: far fields)
                            instead of keeping them in workgroup scratch */

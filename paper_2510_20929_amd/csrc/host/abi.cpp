@@ -425,7 +425,7 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > 3 || tune->grid < 0 || tune->plain_chunk < 0 ||
+  if (tune && (tune->variant < 0 || tune->variant > 4 || tune->grid < 0 || tune->plain_chunk < 0 ||
                tune->recompute < 0))
     return PTYHIP_EINVAL;
   Plan* p = new (std::nothrow) Plan();

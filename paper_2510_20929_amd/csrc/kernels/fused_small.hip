@@ -5,10 +5,10 @@
 
 namespace ptyhip {
 
-template <int N, int T, int LOSS, bool RV>
+template <int N, int T, int LOSS, bool RV, bool GOREG = RV>
 __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   __shared__ SmallShared<N, T> sh;
-  small_body<N, T, LOSS, RV>(a, sh, blockIdx.x, gridDim.x);
+  small_body<N, T, LOSS, RV, GOREG>(a, sh, blockIdx.x, gridDim.x);
 }
 
 template <int N, int T, int LOSS>
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void probe_reduce_kernel(const float2* __restr
 }
 
 // ----------------------------------------------------------------------------- launchers
-template <int N, int T, bool RV = false>
+template <int N, int T, bool RV = false, bool GOREG = RV>
 static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   const bool ms = a.S > 1;
   if (a.near) {
@@ -257,10 +257,10 @@ static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   }
   if (a.loss == 0) {
     if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
   } else {
     if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1, RV>), dim3(grid), dim3(T), 0, st, a);
+    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -276,13 +276,15 @@ static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, i
 
 // variants: 0 = 512 threads, scratch-resident patch; 1 = 1024 (128^2) or 256 (64^2)
 // threads, scratch-resident patch; 2 = 512 threads, register-resident patch;
-// 3 = 1024 (128^2) or 256 (64^2) threads, register-resident patch
+// 3 = 1024 (128^2) or 256 (64^2) threads, register-resident patch and patch gradient;
+// 4 = as 3 with the patch gradient in scratch
 int fused_small_threads(int N, int variant) {
+  const bool wide = variant == 1 || variant == 3 || variant == 4;
   switch (N) {
     case 16: return 64;
     case 32: return 128;
-    case 64: return (variant == 1 || variant == 3) ? 256 : 512;
-    case 128: return (variant == 1 || variant == 3) ? 1024 : 512;
+    case 64: return wide ? 256 : 512;
+    case 128: return wide ? 1024 : 512;
     default: return 0;
   }
 }
@@ -295,6 +297,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
   if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
   else if (near) base = fr * (2 + size_t(M));
   else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
+  else if (variant == 4 && N >= 64) base = fr / 2 + fr + (recompute ? 0 : fr * size_t(M - 1));
   else base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
   *pacc_off = base;
   return base + fr * size_t(E) * M;
@@ -307,11 +310,13 @@ hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, h
     case 64:
       if (variant == 1) return launch_small_t<64, 256>(a, grid, st);
       if (variant == 3) return launch_small_t<64, 256, true>(a, grid, st);
+      if (variant == 4) return launch_small_t<64, 256, true, false>(a, grid, st);
       if (variant == 2) return launch_small_t<64, 512, true>(a, grid, st);
       return launch_small_t<64, 512>(a, grid, st);
     case 128:
       if (variant == 1) return launch_small_t<128, 1024>(a, grid, st);
       if (variant == 3) return launch_small_t<128, 1024, true>(a, grid, st);
+      if (variant == 4) return launch_small_t<128, 1024, true, false>(a, grid, st);
       if (variant == 2) return launch_small_t<128, 512, true>(a, grid, st);
       return launch_small_t<128, 512>(a, grid, st);
     default: return hipErrorInvalidValue;

@@ -294,7 +294,9 @@ struct SmallShared {
 // RV = true (512 threads): o and the running patch gradient stay in registers and only
 // dl/dI (fp32) is parked in scratch between its uses, which removes most of the
 // scratch traffic at the price of about twice the registers.
-template <int N, int T, int LOSS, bool RV = false>
+// GOREG (with RV): the running patch gradient also stays in registers; without it, it
+// lives in scratch (fewer registers across the transforms).
+template <int N, int T, int LOSS, bool RV = false, bool GOREG = RV>
 __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>& sh, int wg, int nwg) {
   using F = Frame2D<N, T>;
   using C = SmallCtx<N, T>;
@@ -317,8 +319,9 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
   // accumulator at pacc_off
   float2* scr = a.scratch + size_t(wg) * a.scratch_stride;
   const BufFrame sb(scr, uint32_t(a.scratch_stride * sizeof(float2)));
-  constexpr int GACC_B = C::NN * 8;
-  constexpr int PSIS_B = (RV ? C::NN / 2 : 2 * C::NN) * 8;
+  constexpr bool GO_IN_REGS = RV && GOREG;
+  constexpr int GACC_B = (RV ? C::NN / 2 : C::NN) * 8;
+  constexpr int PSIS_B = (RV ? (GO_IN_REGS ? C::NN / 2 : C::NN / 2 + C::NN) : 2 * C::NN) * 8;
   const int pacc_b = int(a.pacc_off * sizeof(float2));
   if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
 
@@ -389,9 +392,9 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
     }
 
     // adjoint, last mode first (its far field is still in registers)
-    float2 go[RV ? E : 1];
+    float2 go[GO_IN_REGS ? E : 1];
 #pragma unroll
-    for (int i = 0; i < (RV ? E : 1); ++i) go[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < (GO_IN_REGS ? E : 1); ++i) go[i] = make_float2(0.f, 0.f);
     for (int mm = 0; mm < a.M; ++mm) {
       const int m = a.M - 1 - mm;
       if (!fwd) {
@@ -430,7 +433,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
           constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
           for_probe<N, T, (RV ? 4 : 0)>(a, wk, m, t, [&](int i, float2 P) {
             float2 g = cmulc(P, v[i]);
-            if constexpr (RV) {
+            if constexpr (GO_IN_REGS) {
               if constexpr (!FIRST) g = cadd(g, go[i]);
               go[i] = g;
             } else {

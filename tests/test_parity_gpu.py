@@ -87,7 +87,7 @@ def test_frame512(plain):
     compare(got, ref, grads, tag=f"N=512 {'plain' if plain else 'fused'}")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("recompute", [0, 1])
 @pytest.mark.parametrize("N", [64, 128])
 def test_fused_variants(N, variant, recompute):
