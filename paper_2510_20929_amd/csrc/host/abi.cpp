@@ -140,8 +140,22 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   const size_t win_budget = size_t(2) << 30;
   p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(maxK, 1)), win_budget / win)));
   if (p->whole_windows) p->fchunk = std::max(maxK, 1);
+  // large frames with several eigenprobes: the fused kernel stages each position's
+  // probe-wave gradients and a separate pass forms sum_k w_k,e gP_k for every eigenprobe
+  // (one write per pixel instead of E read-modify-writes); chunk bounded to 2 GiB
+  const bool stage = !p->on_chip && S == 1 && E > 1 && !p->whole_windows;
+  if (stage) {
+    const size_t per = size_t(M) * NN * sizeof(float2);
+    p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(p->fchunk), win_budget / per)));
+    const size_t part1 = size_t(E) * M * NN * sizeof(float2);
+    p->eig_splits = int(std::max<size_t>(1, std::min<size_t>(8, (size_t(256) << 20) / part1)));
+  }
   if ((st = dalloc(p, &p->gwin, size_t(p->fchunk) * S * (N + 1) * (N + 1))) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->wvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
+  if (stage) {
+    if ((st = dalloc(p, &p->gpstage, size_t(p->fchunk) * M * NN)) != PTYHIP_OK) return st;
+    if ((st = dalloc(p, &p->eig_part, size_t(p->eig_splits) * E * M * NN)) != PTYHIP_OK) return st;
+  }
   p->window_bytes = size_t(p->fchunk) * win;
 
   // per-step path buffers, chunked to a bounded footprint
@@ -309,6 +323,8 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
   for (int k0 = 0; k0 < a.K; k0 += p->fchunk) {
     const int n = std::min(p->fchunk, a.K - k0);
     CallArgs c = chunk_args(a, k0, n, N, d.n_eig, d.n_modes);
+    const bool staged = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
+    c.gpstage = staged ? p->gpstage : nullptr;
     timing_begin(p, st);
     hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, p->grid, st)
                               : launch_fused_big(c, N, p->grid, st);
@@ -328,8 +344,14 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
       g.accumulate = (acc || k0 > 0) ? 1 : 0;
       if (launch_window_gather(g, st) != hipSuccess) return PTYHIP_EHIP;
     }
+    if (c.gpstage &&
+        launch_eig_stage_reduce(p->gpstage, c.weights, p->wvalid, n, d.n_eig, d.n_modes, N, p->eig_splits,
+                                p->eig_part, reinterpret_cast<float2*>(g_probe), (acc || k0 > 0) ? 1 : 0,
+                                st) != hipSuccess)
+      return PTYHIP_EHIP;
   }
-  if (want_probe) {
+  const bool staged_all = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
+  if (want_probe && !staged_all) {
     hipError_t e = p->on_chip
                        ? launch_probe_reduce_small(a, N, p->tune.variant, p->grid, reinterpret_cast<float2*>(g_probe),
                                                    acc ? 1 : 0, st)

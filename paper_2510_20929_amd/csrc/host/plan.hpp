@@ -27,6 +27,9 @@ struct Plan {
   float2* tf = nullptr;
   float2* tfd = nullptr;      // near field: transfer function to the detector
   double* lz_part = nullptr;  // near field: per-position dL/d(det_lambda_z)
+  float2* gpstage = nullptr;  // large frames with eigenprobes: staged probe-wave gradients [fchunk][M][N][N]
+  float2* eig_part = nullptr; // their split partial sums [splits][E][M][N][N]
+  int eig_splits = 0;
   uint32_t* flags = nullptr;
   double* loss_part = nullptr;
   double* pos_part = nullptr;

@@ -36,6 +36,8 @@ struct CallArgs {
   double* pos_part;       // [K][2]
   double* w_part;         // [K][E]
   double* lz_part;        // near field: [K] dL/d(lambda z_det) per position
+  float2* gpstage;        // large frames, several eigenprobes: per-position probe-wave gradients
+                          // [K][M][N][N] for the staged eigenprobe reduction, or nullptr
   uint32_t* flags;        // device error latch
   // tables and workspace
   const float2* tw;       // W_N^j, j in [0, N)

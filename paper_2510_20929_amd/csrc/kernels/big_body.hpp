@@ -71,7 +71,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   float2* Ps = Fr + NN;
   float* cf = reinterpret_cast<float*>(Ps + size_t(M) * NN);
   float2* pacc = scr + a.pacc_off;
-  if (adj && a.zero_acc && want_probe)
+  if (adj && a.zero_acc && want_probe && !a.gpstage)
     for (size_t i = tid; i < size_t(a.E) * M * NN; i += T) pacc[i] = make_float2(0.f, 0.f);
 
   for (int k = wg; k < a.K; k += nwg) {
@@ -194,7 +194,9 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           G[pix] = m == 0 ? go : cadd(G[pix], go);
           const float2 gP = cmulc(O[pix], g);
           tile[(i / N) * RP + (i % N)] = gP;
-          if (want_probe) {
+          if (want_probe && a.gpstage) {
+            a.gpstage[(size_t(k) * M + m) * NN + pix] = gP;
+          } else if (want_probe) {
             const int ne = wk ? a.E : 1;
             for (int e = 0; e < ne; ++e) {
               float2& acc = pacc[(size_t(e) * M + m) * NN + pix];

@@ -47,6 +47,60 @@ __global__ __launch_bounds__(256) void probe_reduce_big_kernel(const float2* __r
   }
 }
 
+// Eigenprobe gradients from staged probe-wave gradients of a chunk of n positions:
+// part[s][e][m][p] = sum over the positions kk of split s of w[kk][e] gP[kk][m][p]
+// (positions without a valid window are skipped); then the splits are added in order.
+__global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict__ gp, const float* __restrict__ w,
+                                                        const int* __restrict__ valid, int n, int E, int M, int NN,
+                                                        int splits, float2* __restrict__ part) {
+  const size_t MN = size_t(M) * NN;
+  const int s = blockIdx.y;
+  const int per = (n + splits - 1) / splits;
+  const int k0 = s * per, k1 = min(n, k0 + per);
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < MN; g += size_t(gridDim.x) * blockDim.x) {
+    float2 acc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (int kk = k0; kk < k1; ++kk) {
+      if (!valid[kk]) continue;
+      const float2 v = gp[size_t(kk) * MN + g];
+      const float* wk = w + size_t(kk) * E;
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (e < E) {
+          acc[e].x = fmaf(wk[e], v.x, acc[e].x);
+          acc[e].y = fmaf(wk[e], v.y, acc[e].y);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      if (e < E) part[(size_t(s) * E + e) * MN + g] = acc[e];
+  }
+}
+
+__global__ void eig_combine_kernel(const float2* __restrict__ part, int splits, size_t total, float2* g_probe,
+                                   int accumulate) {
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+    float2 s = accumulate ? g_probe[g] : make_float2(0.f, 0.f);
+    for (int i = 0; i < splits; ++i) s = cadd(s, part[size_t(i) * total + g]);
+    g_probe[g] = s;
+  }
+}
+
+hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* valid, int n, int E, int M, int N,
+                                   int splits, float2* part, float2* g_probe, int accumulate, hipStream_t st) {
+  const size_t MN = size_t(M) * N * N;
+  size_t bx = (MN + 255) / 256;
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(eig_stage_kernel, dim3(unsigned(bx), unsigned(splits)), dim3(256), 0, st, gp, w, valid, n, E, M,
+                     N * N, splits, part);
+  const size_t total = size_t(E) * MN;
+  size_t b2 = (total + 255) / 256;
+  if (b2 > 16384) b2 = 16384;
+  hipLaunchKernelGGL(eig_combine_kernel, dim3(unsigned(b2)), dim3(256), 0, st, part, splits, total, g_probe, accumulate);
+  return hipGetLastError();
+}
+
 template <int N>
 static hipError_t launch_big_t(const CallArgs& a, int grid, hipStream_t st) {
   if (a.loss == 0) hipLaunchKernelGGL((fused_big_kernel<N, 0>), dim3(grid), dim3(BIG_T), 0, st, a);
