@@ -147,8 +147,12 @@ def kernel_name(plan, prob, tune):
         return "fused_big_kernel<%d, %d>" % (prob.N, loss)
     if prob.S > 1:
         return "fused_small_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
-    rv = "true" if (tune or {}).get("variant") in (2, 3) and prob.N >= 64 else "false"
-    return "fused_small_kernel<%d, %d, %d, %s>" % (prob.N, info["threads"], loss, rv)
+    v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
+    rv = "true" if v in (2, 3, 4) else "false"      # patch in registers
+    goreg = "true" if v in (2, 3) else "false"      # patch gradient in registers
+    if getattr(prob, "det_lambda_z", None) is not None:
+        return "fused_small_near_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
+    return "fused_small_kernel<%d, %d, %d, %s, %s>" % (prob.N, info["threads"], loss, rv, goreg)
 
 
 def measured_intensities(truth, dev, torch, t, Plan):
