@@ -229,8 +229,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the data-parallel sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would shard positions "
+              "and all-reduce the object and probe gradients)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -57,7 +57,7 @@ typedef enum {
   PTYHIP_ENONFINITE = 4,   /* non-finite scalar parameter */
   PTYHIP_EHIP = 5,         /* a HIP runtime call failed */
   PTYHIP_ENOMEM = 6,       /* workspace allocation failed */
-  PTYHIP_EUNSUPPORTED = 7  /* size or option this build does not support */
+  PTYHIP_EUNSUPPORTED = 7  /* size or option the library does not support */
 } ptyhip_status;
 
 typedef enum {

@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void pl_posgrad_kernel(PlainArgs b) {
   }
 }
 
-// ----------------------------------------------------------------------------- driver
+// ----------------------------------------------------------------------------- host loop over the steps
 static inline dim3 pix_grid(int NN, int rows) { return dim3(unsigned((NN + 255) / 256), unsigned(rows)); }
 
 hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
