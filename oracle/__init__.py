@@ -17,6 +17,9 @@ from .ptycho_ref import (  # noqa: F401
     fft2u,
     forward,
     forward_adjoint,
+    fourier_patch,
+    fourier_scatter,
+    shift_phase,
     fresnel_tf,
     ifft2u,
     illumination,

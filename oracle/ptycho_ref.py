@@ -140,6 +140,36 @@ def patch_derivatives(Os: np.ndarray, y0: int, x0: int, fy: float, fx: float, N:
     return dy, dx
 
 
+# Fourier-shift variant of the sub-pixel patch: the N x N window at the integer corner,
+# shifted by the fraction (fy, fx) with the shift theorem (periodic within the window).
+
+def shift_phase(N: int, fy: float, fx: float) -> np.ndarray:
+    """exp(2 pi i (ky fy + kx fx) / N) on the unshifted grid, k the signed frequency index."""
+    k = np.fft.fftfreq(N) * N
+    return np.exp(2j * math.pi * (k[:, None] * fy + k[None, :] * fx) / N)
+
+
+def fourier_patch(Os: np.ndarray, y0: int, x0: int, fy: float, fx: float, N: int) -> np.ndarray:
+    """Patch o(y, x) = O(y0 + fy + y, x0 + fx + x) by the shift theorem on the window."""
+    w = Os[y0:y0 + N, x0:x0 + N].astype(np.complex128)
+    return ifft2u(fft2u(w) * shift_phase(N, fy, fx))
+
+
+def fourier_scatter(gOs: np.ndarray, g: np.ndarray, y0: int, x0: int, fy: float, fx: float) -> None:
+    """Transpose of ``fourier_patch``: add the window gradient back into the slice."""
+    N = g.shape[-1]
+    gOs[y0:y0 + N, x0:x0 + N] += ifft2u(fft2u(g) * np.conj(shift_phase(N, fy, fx)))
+
+
+def fourier_derivatives(Os: np.ndarray, y0: int, x0: int, fy: float, fx: float, N: int):
+    """d(patch)/dy and d(patch)/dx of the Fourier-shifted patch (spectral derivative)."""
+    k = np.fft.fftfreq(N) * N
+    X = fft2u(Os[y0:y0 + N, x0:x0 + N].astype(np.complex128)) * shift_phase(N, fy, fx)
+    dy = ifft2u(X * (2j * math.pi * k[:, None] / N))
+    dx = ifft2u(X * (2j * math.pi * k[None, :] / N))
+    return dy, dx
+
+
 def probe_for_position(U: np.ndarray, w_k: Optional[np.ndarray]) -> np.ndarray:
     """Scan-point probe modes [M, N, N]: the weighted sum of the eigenprobes."""
     if w_k is None:
@@ -180,11 +210,12 @@ def _as_inputs(obj, probe, positions, weights):
     return O, U, r, w
 
 
-def _forward_one(O, P, y0, x0, fy, fx, tf):
+def _forward_one(O, P, y0, x0, fy, fx, tf, subpixel="bilinear"):
     """Exit waves of one position. Returns (patches o_s, incident waves psi_s [M,N,N]
     per slice, far-field Psi [M,N,N])."""
     S, N = O.shape[0], P.shape[-1]
-    patches = [extract_patch(O[s], y0, x0, fy, fx, N) for s in range(S)]
+    ext = fourier_patch if subpixel == "fourier" else extract_patch
+    patches = [ext(O[s], y0, x0, fy, fx, N) for s in range(S)]
     psis = []
     psi = P
     for s in range(S):
@@ -210,7 +241,7 @@ def apply_A(obj, probe, positions, weights=None, lambda_z: float = 0.0) -> np.nd
 
 
 def _backward_one(O, U, w_k, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
-                  gO, gU, want_w: bool):
+                  gO, gU, want_w: bool, subpixel="bilinear"):
     """Adjoint of one position given dL/dPsi (g convention) for every mode.
     Accumulates into gO, gU; returns (per-slice patch gradients, dL/dw_k)."""
     S = O.shape[0]
@@ -231,8 +262,9 @@ def _backward_one(O, U, w_k, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
     gw = None
     if want_w:
         gw = np.array([float(np.sum(np.real(np.conj(gP) * U[e]))) for e in range(U.shape[0])])
+    scat = fourier_scatter if subpixel == "fourier" else scatter_patch
     for s in range(S):
-        scatter_patch(gO[s], g_patch[s], y0, x0, fy, fx)
+        scat(gO[s], g_patch[s], y0, x0, fy, fx)
     return g_patch, gw
 
 
@@ -256,18 +288,19 @@ def apply_AH(Y, obj, probe, positions, weights=None, lambda_z: float = 0.0):
 
 def forward(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
             eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None,
-            det_lambda_z: Optional[float] = None):
+            det_lambda_z: Optional[float] = None, subpixel: str = "bilinear"):
     """Loss L and the predicted intensity I_pred [K, N, N] (DC-centred in the far field,
     natural pixel order in the near field)."""
     out = forward_adjoint(obj, probe, positions, I_meas, weights=weights, loss=loss, eps=eps,
-                          lambda_z=lambda_z, norm_count=norm_count, grads=(), det_lambda_z=det_lambda_z)
+                          lambda_z=lambda_z, norm_count=norm_count, grads=(), det_lambda_z=det_lambda_z,
+                          subpixel=subpixel)
     return out["loss"], out["I_pred"]
 
 
 def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = "amplitude",
                     eps: float = 1e-3, lambda_z: float = 0.0, norm_count: Optional[float] = None,
                     grads: Sequence[str] = ("obj", "probe"),
-                    det_lambda_z: Optional[float] = None) -> Dict[str, np.ndarray]:
+                    det_lambda_z: Optional[float] = None, subpixel: str = "bilinear") -> Dict[str, np.ndarray]:
     """Loss, predicted intensity and the requested gradients
     (any of "obj", "probe", "pos", "weights", and "lambda_z" in the near field).
 
@@ -275,8 +308,15 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
     design, Overview): the last exit wave chi is carried to the detector by Fresnel
     propagation, Psi = F^-1(H F chi) with H = exp(-i pi lz_det (fy^2 + fx^2)), instead of
     the far-field transform; the detector is in natural pixel order. "lambda_z" asks for
-    dL/d(lz_det) = sum_k,m Re sum_f conj(F g_Psi) (-i pi (fy^2 + fx^2)) H F chi."""
+    dL/d(lz_det) = sum_k,m Re sum_f conj(F g_Psi) (-i pi (fy^2 + fx^2)) H F chi.
+
+    subpixel="fourier": the patch is the N x N window at the integer corner shifted by
+    the fraction with the shift theorem (``fourier_patch``) instead of bilinear
+    interpolation; the window is never widened."""
     near = det_lambda_z is not None
+    if subpixel not in ("bilinear", "fourier"):
+        raise ValueError(f"unknown subpixel model {subpixel!r}")
+    fourier = subpixel == "fourier"
     O, U, r, w = _as_inputs(obj, probe, positions, weights)
     Im_all = np.asarray(I_meas).astype(np.float64)
     K, N = r.shape[0], U.shape[-1]
@@ -302,10 +342,12 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
     I_pred = np.empty((K, N, N))
     total = 0.0
     for k in range(K):
-        y0, x0, fy, fx = split_position(r[k], N, H, W, want_pos)
+        y0, x0, fy, fx = split_position(r[k], N, H, W, want_pos and not fourier)
+        if fourier and (y0 + N > H or x0 + N > W):
+            raise ValueError(f"scan window at {tuple(r[k])} leaves the {H}x{W} object")
         wk = None if w is None else w[k]
         P = probe_for_position(U, wk)
-        patches, psis, Psi = _forward_one(O, P, y0, x0, fy, fx, tf)
+        patches, psis, Psi = _forward_one(O, P, y0, x0, fy, fx, tf, subpixel)
         if near:
             X = Psi                                   # F chi of the last exit wave
             Psi = ifft2u(tf_det * X)                  # detector-plane wave
@@ -323,12 +365,12 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
                 g_lz += float(np.sum(np.real(np.conj(Gd) * (-1j * math.pi * q2) * tf_det * X)))
             gPsi = np.conj(tf_det) * Gd               # far-field-domain gradient of chi
         g_patch, gwk = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
-                                     gO, gU, want_w)
+                                     gO, gU, want_w, subpixel)
         if want_w:
             gw[k] = gwk
         if want_pos:
             for s in range(S):
-                dy, dx = patch_derivatives(O[s], y0, x0, fy, fx, N)
+                dy, dx = (fourier_derivatives if fourier else patch_derivatives)(O[s], y0, x0, fy, fx, N)
                 gr[k, 0] += float(np.sum(np.real(np.conj(g_patch[s]) * dy)))
                 gr[k, 1] += float(np.sum(np.real(np.conj(g_patch[s]) * dx)))
     out: Dict[str, np.ndarray] = {"loss": total * scale, "I_pred": I_pred}
