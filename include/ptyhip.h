@@ -77,6 +77,14 @@ enum {
   PTYHIP_GRAD_LAMBDA_Z = 128  /* near field: dL/d(det_lambda_z), device double[1] */
 };
 
+/* sub-pixel patch model (Software design, Overview: patch extraction is a shared routine;
+ * the paper names no interpolation) */
+typedef enum {
+  PTYHIP_SUBPIXEL_BILINEAR = 0, /* bilinear taps over the (N+1)^2 window */
+  PTYHIP_SUBPIXEL_FOURIER = 1   /* o = F^-1(exp(2 pi i (ky fy + kx fx) / N) F window), window at the
+                                   integer corner, periodic within the window */
+} ptyhip_subpixel;
+
 /* propagation to the detector */
 typedef enum {
   PTYHIP_PROP_FAR = 0, /* far field: unitary 2D DFT, DC-centred detector */
@@ -102,6 +110,9 @@ typedef struct {
                            forward model (Software design, Overview); near needs S == 1, N <= 128 */
   float det_lambda_z;   /* near field: wavelength times detector distance, px^2; the detector
                            wave is F^-1(exp(-i pi det_lambda_z (fy^2 + fx^2)) F chi) */
+  int32_t subpixel;     /* a ptyhip_subpixel value: bilinear interpolation (default) or the
+                           Fourier shift of the integer N x N window; Fourier needs S == 1,
+                           N <= 128 and the far field */
 } ptyhip_desc;
 
 /* Optional implementation choices (the autotuner's search space). Zero = default. */

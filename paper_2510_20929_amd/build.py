@@ -19,6 +19,7 @@ LIB = os.path.join(HERE, "libptyhip.so")
 SOURCES = [
     "kernels/plain.hip",
     "kernels/fused_small.hip",
+    "kernels/fused_small_fs.hip",
     "kernels/fused_big.hip",
     "kernels/finalize.hip",
     "kernels/gather.hip",

@@ -121,7 +121,8 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if (p->on_chip) {
     p->threads = fused_small_threads(N, p->tune.variant);
     p->scratch_stride = fused_small_scratch_elems(N, S, M, E, recompute, &p->pacc_off, p->tune.variant,
-                                                  d.propagation == PTYHIP_PROP_NEAR);
+                                                  d.propagation == PTYHIP_PROP_NEAR,
+                                                  d.subpixel == PTYHIP_SUBPIXEL_FOURIER);
   } else {
     p->threads = 256;
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
@@ -204,6 +205,10 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
     if (!std::isfinite(d->det_lambda_z)) return PTYHIP_ENONFINITE;
     if (d->n_slices > 1 || d->frame > 128) return PTYHIP_EUNSUPPORTED;
   }
+  if (d->subpixel != PTYHIP_SUBPIXEL_BILINEAR && d->subpixel != PTYHIP_SUBPIXEL_FOURIER) return PTYHIP_EINVAL;
+  if (d->subpixel == PTYHIP_SUBPIXEL_FOURIER &&
+      (d->n_slices > 1 || d->frame > 128 || d->propagation != PTYHIP_PROP_FAR))
+    return PTYHIP_EUNSUPPORTED;
   return PTYHIP_OK;
 }
 
@@ -236,6 +241,7 @@ CallArgs make_args(const Plan* p, int K, int mode, bool fused, const float* obj,
   a.tf = p->tf;
   a.tfd = p->tfd;
   a.near = d.propagation == PTYHIP_PROP_NEAR ? 1 : 0;
+  a.fshift = d.subpixel == PTYHIP_SUBPIXEL_FOURIER ? 1 : 0;
   a.scratch = p->scratch;
   a.scratch_stride = p->scratch_stride;
   a.pacc_off = p->pacc_off;
@@ -378,7 +384,7 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   const bool near = d.propagation == PTYHIP_PROP_NEAR;
   const bool want_lz = !forward_only && (flags & PTYHIP_GRAD_LAMBDA_Z);
   if (want_lz && (!near || !g_lz)) return PTYHIP_EINVAL;
-  if (near && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
+  if ((near || d.subpixel == PTYHIP_SUBPIXEL_FOURIER) && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;
   if (want_pos && K > 0 && !g_pos) return PTYHIP_EINVAL;
@@ -610,7 +616,7 @@ ptyhip_status ptyhip_apply_A(ptyhip_plan plan, void* stream, int32_t K, const fl
                              const float* weights, const float* positions, float* Psi) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
-  if (p->d.propagation == PTYHIP_PROP_NEAR) return PTYHIP_EUNSUPPORTED;
+  if (p->d.propagation == PTYHIP_PROP_NEAR || p->d.subpixel == PTYHIP_SUBPIXEL_FOURIER) return PTYHIP_EUNSUPPORTED;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   if (!obj || !probe || (K > 0 && (!positions || !Psi))) return PTYHIP_EINVAL;
   if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;
@@ -627,7 +633,7 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
                               float* g_probe) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return PTYHIP_EINVAL;
-  if (p->d.propagation == PTYHIP_PROP_NEAR) return PTYHIP_EUNSUPPORTED;
+  if (p->d.propagation == PTYHIP_PROP_NEAR || p->d.subpixel == PTYHIP_SUBPIXEL_FOURIER) return PTYHIP_EUNSUPPORTED;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   if (!obj || !probe || (K > 0 && (!Y || !positions))) return PTYHIP_EINVAL;
   if (p->d.n_eig > 1 && K > 0 && !weights) return PTYHIP_EINVAL;

@@ -62,7 +62,9 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     ptyhip_status s = validate_desc(&descs[i]);
     if (s != PTYHIP_OK) return s;
     const int N = descs[i].frame;
-    if (N < 64 || descs[i].n_slices != 1 || descs[i].propagation != PTYHIP_PROP_FAR) return PTYHIP_EUNSUPPORTED;
+    if (N < 64 || descs[i].n_slices != 1 || descs[i].propagation != PTYHIP_PROP_FAR ||
+        descs[i].subpixel != PTYHIP_SUBPIXEL_BILINEAR)
+      return PTYHIP_EUNSUPPORTED;
     if (K[i] < 0) return PTYHIP_EBOUNDS;
   }
   auto* b = new (std::nothrow) ptyhip_batch_s();

@@ -57,6 +57,7 @@ struct CallArgs {
   int mode;               // CallMode
   int recompute;          // multislice: recompute incident waves instead of storing them
   int near;               // 1: near-field detector (Fresnel propagation, natural pixel order)
+  int fshift;             // 1: Fourier-shift sub-pixel patch instead of bilinear
 };
 
 }  // namespace ptyhip

@@ -291,11 +291,12 @@ int fused_small_threads(int N, int variant) {
 
 // per-workgroup scratch (float2 elements) and the offset of the probe accumulator
 size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant,
-                                 bool near) {
+                                 bool near, bool fshift) {
   const size_t fr = size_t(N) * N;
   size_t base;
   if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
   else if (near) base = fr * (2 + size_t(M));
+  else if (fshift) base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1) + fr;  // + shifted window spectrum
   else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
   else if (variant == 4 && N >= 64) base = fr / 2 + fr + (recompute ? 0 : fr * size_t(M - 1));
   else base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
@@ -304,6 +305,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
 }
 
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st) {
+  if (a.fshift) return launch_fused_small_fs(a, N, fused_small_threads(N, variant), grid, st);
   switch (N) {
     case 16: return launch_small_t<16, 64>(a, grid, st);
     case 32: return launch_small_t<32, 128>(a, grid, st);

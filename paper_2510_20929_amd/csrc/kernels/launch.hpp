@@ -69,8 +69,9 @@ hipError_t run_plain_chunk(PlainArgs b, hipStream_t st);
 
 int fused_small_threads(int N, int variant);
 size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size_t* pacc_off, int variant,
-                                 bool near = false);
+                                 bool near = false, bool fshift = false);
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
+hipError_t launch_fused_small_fs(const CallArgs& a, int N, int threads, int grid, hipStream_t st);
 hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
                                      int accumulate, hipStream_t st);
 

@@ -296,11 +296,17 @@ struct SmallShared {
 // scratch traffic at the price of about twice the registers.
 // GOREG (with RV): the running patch gradient also stays in registers; without it, it
 // lives in scratch (fewer registers across the transforms).
-template <int N, int T, int LOSS, bool RV = false, bool GOREG = RV>
+// FS: Fourier-shift sub-pixel patch (the integer window shifted by the fraction with
+// the shift theorem) instead of bilinear interpolation; the window gradient is the
+// inverse shift of the patch gradient and the position gradient is taken spectrally.
+// Uses one more scratch frame (the shifted window spectrum) just below the probe
+// accumulator.
+template <int N, int T, int LOSS, bool RV = false, bool GOREG = RV, bool FS = false>
 __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>& sh, int wg, int nwg) {
   using F = Frame2D<N, T>;
   using C = SmallCtx<N, T>;
   constexpr int E = C::E;
+  static_assert(!(FS && RV), "the Fourier-shift patch uses the scratch-resident layout");
   float2* lds = sh.lds;
   float2* tws = sh.tws;
   double* red = sh.red;
@@ -323,10 +329,22 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
   constexpr int GACC_B = (RV ? C::NN / 2 : C::NN) * 8;
   constexpr int PSIS_B = (RV ? (GO_IN_REGS ? C::NN / 2 : C::NN / 2 + C::NN) : 2 * C::NN) * 8;
   const int pacc_b = int(a.pacc_off * sizeof(float2));
+  const int fsx_b = pacc_b - C::NN * 8;  // FS: shifted window spectrum
   if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  // FS: shift phase exp(2 pi i (ky fy + kx fx) / N) of element i (layout D) and the
+  // signed frequencies 2 pi k / N
+  auto shift_of = [&](const PosInfo& p, int t, int i, float& cy, float& cx) {
+    const int l = i / C::N2, ii = i % C::N2;
+    const int ky = F::d_ky(t, l, ii), kx = F::d_kx(t, l);
+    cy = 6.283185307179586f * float(ky < N / 2 ? ky : ky - N) / float(N);
+    cx = 6.283185307179586f * float(kx < N / 2 ? kx : kx - N) / float(N);
+    float s, c;
+    sincosf(cy * p.fy + cx * p.fx, &s, &c);
+    return make_float2(c, s);
+  };
 
   for (int k = wg; k < a.K; k += nwg) {
-    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos && !FS);
     if (!p.ok) {
       skip_position<N, T>(a, k, p);
       continue;
@@ -338,7 +356,33 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
     const float* wk = a.weights ? wsh : nullptr;
 
     float2 o[RV ? E : 1];
-    {
+    if constexpr (FS) {
+      float2 w[E];
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int l = i / C::N2, j = i % C::N2;
+          w[i] = a.obj[size_t(p.y0 + F::a_y(t, l)) * a.W + (p.x0 + F::a_x(t, l, j))];
+        }
+      }
+      F::forward(w, lds, tws, inv_n);
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          float cy, cx;
+          w[i] = cmul(w[i], shift_of(p, t, i, cy, cx));
+          if (want_pos) sb.st(w[i], t * 8, fsx_b + i * T * 8);
+        }
+      }
+      F::inverse(w, lds, tws, inv_n);
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) sb.st(w[i], t * 8, i * T * 8);
+      }
+    } else {
       const int t = opaque_tid();
 #pragma unroll
       for (int i = 0; i < E; ++i) {
@@ -462,7 +506,55 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
 
     __syncthreads();
     double gy = 0.0, gx = 0.0;
-    window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);
+    if constexpr (FS) {
+      // LDS holds the patch gradient g_o (natural order): G = F g_o, the position
+      // gradient Re sum conj(G) (2 pi i k / N) S X, then the window gradient F^-1(conj(S) G)
+      float2 w[E];
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int pix = C::a_pix(t, i);
+          w[i] = lds[(pix / N) * F::P + (pix % N)];
+        }
+      }
+      F::forward(w, lds, tws, inv_n);
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          float cy, cx;
+          const float2 s = shift_of(p, t, i, cy, cx);
+          if (want_pos) {
+            const float2 z = sb.ld(t * 8, fsx_b + i * T * 8);
+            const float q = w[i].y * z.x - w[i].x * z.y;
+            gy += double(cy * q);
+            gx += double(cx * q);
+          }
+          w[i] = cmulc(s, w[i]);
+        }
+      }
+      F::inverse(w, lds, tws, inv_n);
+      __syncthreads();
+      {
+        const int t = opaque_tid();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          const int pix = C::a_pix(t, i);
+          lds[(pix / N) * F::P + (pix % N)] = w[i];
+        }
+      }
+      __syncthreads();
+      float2* gw = a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr;
+      if ((a.want & WANT_OBJ) && gw) {
+        for (int idx = threadIdx.x; idx < C::WN * C::WN; idx += T) {
+          const int py = idx / C::WN, px = idx - py * C::WN;
+          gw[idx] = (py < N && px < N) ? lds[py * F::P + px] : make_float2(0.f, 0.f);
+        }
+      }
+    } else {
+      window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * C::WN * C::WN : nullptr, gy, gx);
+    }
     finish_position<N, T>(a, k, gy, gx, red, wacc);
   }
 }

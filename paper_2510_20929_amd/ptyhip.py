@@ -46,7 +46,8 @@ class Desc(ctypes.Structure):
     _fields_ = [("frame", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("n_eig", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("obj_h", ctypes.c_int32), ("obj_w", ctypes.c_int32),
                 ("loss", ctypes.c_int32), ("poisson_eps", ctypes.c_float), ("lambda_z", ctypes.c_float),
-                ("norm_count", ctypes.c_double), ("propagation", ctypes.c_int32), ("det_lambda_z", ctypes.c_float)]
+                ("norm_count", ctypes.c_double), ("propagation", ctypes.c_int32), ("det_lambda_z", ctypes.c_float),
+                ("subpixel", ctypes.c_int32)]
 
 
 class Tune(ctypes.Structure):
@@ -121,13 +122,14 @@ def _check(status: int, what: str):
 
 
 def make_desc(frame, n_modes=1, n_eig=1, n_slices=1, obj_h=0, obj_w=0, loss="amplitude", poisson_eps=1e-3,
-              lambda_z=0.0, norm_count=0.0, det_lambda_z=None) -> Desc:
-    """det_lambda_z=None: far-field detector; a number: near-field (Fresnel) detector."""
+              lambda_z=0.0, norm_count=0.0, det_lambda_z=None, subpixel="bilinear") -> Desc:
+    """det_lambda_z=None: far-field detector; a number: near-field (Fresnel) detector.
+    subpixel: "bilinear" or "fourier" (shift theorem on the integer window)."""
     lc = {"amplitude": LOSS_AMPLITUDE, "poisson": LOSS_POISSON}.get(loss, loss)
     near = det_lambda_z is not None
     return Desc(int(frame), int(n_modes), int(n_eig), int(n_slices), int(obj_h), int(obj_w), int(lc),
                 float(poisson_eps), float(lambda_z), float(norm_count), PROP_NEAR if near else PROP_FAR,
-                float(det_lambda_z) if near else 0.0)
+                float(det_lambda_z) if near else 0.0, {"bilinear": 0, "fourier": 1}.get(subpixel, subpixel))
 
 
 def ptyhip_desc_validate(desc: Desc) -> int:
@@ -164,9 +166,9 @@ class Plan:
 
     def __init__(self, frame, n_modes=1, n_eig=1, n_slices=1, obj_h=0, obj_w=0, loss="amplitude",
                  poisson_eps=1e-3, lambda_z=0.0, norm_count=0.0, max_positions=1, tune: Optional[dict] = None,
-                 det_lambda_z=None):
+                 det_lambda_z=None, subpixel="bilinear"):
         self.desc = make_desc(frame, n_modes, n_eig, n_slices, obj_h, obj_w, loss, poisson_eps, lambda_z, norm_count,
-                              det_lambda_z)
+                              det_lambda_z, subpixel)
         self.max_positions = int(max_positions)
         h = ctypes.c_void_p()
         if tune:
@@ -185,7 +187,8 @@ class Plan:
     def for_problem(cls, prob, max_positions=None, norm_count=0.0, tune=None):
         """Plan sized for a synthetic ``synth.Problem``-like object."""
         return cls(prob.N, prob.M, prob.E, prob.S, prob.H, prob.W, prob.loss, prob.eps, prob.lambda_z, norm_count,
-                   max_positions or prob.K, tune, getattr(prob, "det_lambda_z", None))
+                   max_positions or prob.K, tune, getattr(prob, "det_lambda_z", None),
+                   getattr(prob, "subpixel", "bilinear"))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -40,6 +40,7 @@ class Problem:
     lambda_z: float = 0.0           # slice-to-slice Fresnel product, px^2
     grads: Tuple[str, ...] = ("obj", "probe")
     det_lambda_z: Optional[float] = None  # near-field detector (Fresnel), or None: far field
+    subpixel: str = "bilinear"            # sub-pixel patch model: "bilinear" or "fourier"
 
     @property
     def N(self) -> int:

@@ -45,7 +45,8 @@ def measured(truth, seed: int):
     """Noisy measured intensities of a truth problem (clean intensities from the oracle)."""
     _, I_clean = oracle.forward(truth.obj, truth.probe, truth.positions, np.zeros((truth.K, truth.N, truth.N)),
                                 weights=truth.weights, lambda_z=truth.lambda_z,
-                                det_lambda_z=getattr(truth, "det_lambda_z", None))
+                                det_lambda_z=getattr(truth, "det_lambda_z", None),
+                                subpixel=getattr(truth, "subpixel", "bilinear"))
     return W.poisson_counts(I_clean, seed)
 
 
@@ -58,7 +59,8 @@ def case(config: int, seed: int = 5, **kw):
 def run_oracle(prob, I_meas, grads, norm_count=None):
     return oracle.forward_adjoint(prob.obj, prob.probe, prob.positions, I_meas, weights=prob.weights,
                                   loss=prob.loss, eps=prob.eps, lambda_z=prob.lambda_z, norm_count=norm_count,
-                                  grads=grads, det_lambda_z=getattr(prob, "det_lambda_z", None))
+                                  grads=grads, det_lambda_z=getattr(prob, "det_lambda_z", None),
+                                  subpixel=getattr(prob, "subpixel", "bilinear"))
 
 
 def run_gpu(plan, prob, I_meas, grads, plain=False, want_ipred=True):
@@ -88,7 +90,8 @@ def compare(got, ref, grads, tag=""):
     return errs
 
 
-def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=None, det_lambda_z=None):
+def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=None, det_lambda_z=None,
+                   subpixel="bilinear"):
     """Small generic problem (random smooth object, random smooth probes, random
     sub-pixel positions) for shapes no config covers."""
     rng = np.random.default_rng(seed)
@@ -103,7 +106,8 @@ def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=Non
     elif weights == "amp":
         w = rng.uniform(0.85, 1.15, size=(K, E))
     truth = W.Problem("custom", obj.astype(np.complex64), probe.astype(np.complex64), pos.astype(np.float32),
-                      None if w is None else w.astype(np.float32), loss, lambda_z=lz, det_lambda_z=det_lambda_z)
+                      None if w is None else w.astype(np.float32), loss, lambda_z=lz, det_lambda_z=det_lambda_z,
+                      subpixel=subpixel)
     start = W.perturb(truth, seed + 1)
     return start, measured(truth, seed + 2)
 
@@ -111,9 +115,11 @@ def custom_problem(seed, N, M, E, S, H, K, loss="amplitude", lz=0.0, weights=Non
 def _oracle_clean_chunk(args):
     """Worker: the oracle's clean intensities of one chunk of positions (runs in a spawned
     process that never touches the GPU)."""
-    obj, probe, pos, weights, lambda_z, det_lambda_z = args
+    obj, probe, pos, weights, lambda_z, det_lambda_z = args[:6]
+    subpixel = args[6] if len(args) > 6 else "bilinear"
     return oracle.forward(obj, probe, pos, np.zeros((pos.shape[0], probe.shape[-1], probe.shape[-1])),
-                          weights=weights, lambda_z=lambda_z, det_lambda_z=det_lambda_z)[1].astype(np.float32)
+                          weights=weights, lambda_z=lambda_z, det_lambda_z=det_lambda_z,
+                          subpixel=subpixel)[1].astype(np.float32)
 
 
 def measured_many(truths, seeds, workers: int = 16, noise: bool = True):
@@ -130,7 +136,7 @@ def measured_many(truths, seeds, workers: int = 16, noise: bool = True):
         for a, b in zip(bounds[:-1], bounds[1:]):
             w = None if truth.weights is None else truth.weights[a:b]
             jobs.append((truth.obj, truth.probe, truth.positions[a:b], w, truth.lambda_z,
-                         getattr(truth, "det_lambda_z", None)))
+                         getattr(truth, "det_lambda_z", None), getattr(truth, "subpixel", "bilinear")))
             owner.append(t_i)
     import time
     t0 = time.time()

@@ -44,6 +44,11 @@ def test_exports_every_declared_symbol():
     (dict(frame=256, obj_h=600, obj_w=600, det_lambda_z=40.0), 7),            # near field needs N <= 128
     (dict(frame=64, n_slices=2, obj_h=200, obj_w=200, det_lambda_z=40.0), 7),  # and one slice
     (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=float("inf")), 4),
+    (dict(frame=128, obj_h=300, obj_w=300, subpixel="fourier"), 0),
+    (dict(frame=256, obj_h=600, obj_w=600, subpixel="fourier"), 7),            # Fourier shift: N <= 128,
+    (dict(frame=64, n_slices=3, obj_h=200, obj_w=200, subpixel="fourier"), 7), # one slice,
+    (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=5.0, subpixel="fourier"), 7),  # far field
+    (dict(frame=64, obj_h=200, obj_w=200, subpixel=3), 1),
 ])
 def test_desc_validate(kw, status):
     mod = _lib()

@@ -1,0 +1,59 @@
+"""Fourier-shift sub-pixel patch (shift theorem on the integer window) on the GPU
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import compare, custom_problem, dev, rel_l2, run_gpu, run_oracle, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(prob, **kw):
+    torch_cuda()
+    from paper_2510_20929_amd import Plan
+    return Plan.for_problem(prob, **kw)
+
+
+@pytest.mark.parametrize("N,M,E,loss", [(16, 1, 1, "amplitude"), (32, 2, 1, "poisson"), (64, 3, 2, "amplitude"),
+                                        (128, 2, 1, "poisson"), (128, 1, 3, "amplitude")])
+def test_fourier_shift_matches_oracle(N, M, E, loss):
+    start, I = custom_problem(300 + N + M + E, N, M, E, 1, 3 * N, 60, loss=loss, subpixel="fourier",
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads)
+    compare(got, ref, grads, tag=f"fourier N={N} M={M} E={E} {loss}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("recompute", [0, 1])
+def test_fourier_shift_thread_layouts(variant, recompute):
+    start, I = custom_problem(330 + variant, 128, 3, 1, 1, 400, 70, subpixel="fourier")
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute}), start, I, grads)
+    compare(got, ref, grads, tag=f"fourier variant={variant} recompute={recompute}")
+
+
+def test_integer_positions_agree_with_bilinear():
+    import dataclasses
+    start, I = custom_problem(340, 64, 2, 1, 1, 200, 50)
+    start = dataclasses.replace(start, positions=np.floor(start.positions).astype(np.float32))
+    a = run_gpu(_plan(start), start, I, ("obj", "probe"))
+    fs = dataclasses.replace(start, subpixel="fourier")
+    b = run_gpu(_plan(fs), fs, I, ("obj", "probe"))
+    for key in ("loss", "I_pred", "g_obj", "g_probe"):
+        assert rel_l2(b[key], a[key]) <= 1e-5, key
+
+
+def test_fourier_shift_unsupported_forms():
+    torch_cuda()
+    from paper_2510_20929_amd import PtyhipError
+    start, I = custom_problem(341, 32, 1, 1, 1, 100, 10, subpixel="fourier")
+    plan = _plan(start)
+    args = (dev(start.obj), dev(start.probe), dev(start.positions), dev(I))
+    with pytest.raises(PtyhipError):
+        plan.forward_adjoint(*args, grads=("obj",), plain=True)
+    with pytest.raises(PtyhipError):
+        plan.apply_A(args[0], args[1], args[2])
