@@ -351,6 +351,7 @@ def main():
         "cpu_baseline": cpu,
         "tune": tune,
         "tune_source": tune_src,
+        "plan_bytes": {k: plan.info()[k] for k in ("workspace_bytes", "scratch_bytes", "window_bytes", "plain_bytes")},
         "error_flags": flags,
         "kernel_hash": khash,
     })
