@@ -475,7 +475,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
         // loops), then v = conj(o) g_m for the probe gradient
         auto pass = [&](auto first_c, auto last_c) {
           constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
-          for_probe<N, T, (RV ? 4 : 0)>(a, wk, m, t, [&](int i, float2 P) {
+          for_probe<N, T, (GO_IN_REGS ? 4 : 0)>(a, wk, m, t, [&](int i, float2 P) {
             float2 g = cmulc(P, v[i]);
             if constexpr (GO_IN_REGS) {
               if constexpr (!FIRST) g = cadd(g, go[i]);
@@ -501,7 +501,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
           else pass(T0{}, T0{});
         }
       }
-      probe_gradients<N, T, (RV ? 4 : E)>(a, m, wk, v, sb, pacc_b, red, wacc);
+      probe_gradients<N, T, (GO_IN_REGS ? 4 : E)>(a, m, wk, v, sb, pacc_b, red, wacc);
     }
 
     __syncthreads();
