@@ -79,18 +79,22 @@ def read_traffic(khash: str, kernel: str):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(truth, start, budget_s: float = 12.0):
-    """The FP64 oracle (as it stands) on the same workload, single-threaded on the host:
-    forward + adjoint over the positions in chunks of 25, cycling through all positions
-    until the time budget is spent (whole chunks only). Its measured intensities come from
+def cpu_baseline(truth, start, budget_s: float = 10.0, pool_s: float = 8.0):
+    """The FP64 oracle (as it stands) on the same workload on the host: forward + adjoint
+    over the positions in chunks of 25, cycling through all positions until the time
+    budget is spent (whole chunks only). Two legs: one thread in this process, then one
+    single-threaded worker process per available core (at most 16), each on its own shard
+    of the positions. ``value`` is the all-core rate. The measured intensities come from
     the oracle's own forward model of the truth plus Poisson noise."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
+    from oracle import timing
     from synth import workloads as W
 
     n = truth.K
+    kw = dict(loss=start.loss, eps=start.eps, norm_count=truth.K, grads=("obj", "probe", "pos"))
     with threadpool_limits(limits=1):
         _, I_clean = oracle.forward(truth.obj, truth.probe, truth.positions, np.zeros((n, truth.N, truth.N)),
                                     loss=truth.loss)
@@ -99,14 +103,33 @@ def cpu_baseline(truth, start, budget_s: float = 12.0):
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < budget_s:
             k1 = min(k0 + chunk, n)
-            oracle.forward_adjoint(start.obj, start.probe, start.positions[k0:k1], I_meas[k0:k1], loss=start.loss,
-                                   eps=start.eps, norm_count=truth.K, grads=("obj", "probe", "pos"))
+            oracle.forward_adjoint(start.obj, start.probe, start.positions[k0:k1], I_meas[k0:k1], **kw)
             done += k1 - k0
             k0 = 0 if k1 == n else k1
         dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "patterns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} patterns ({done / n:.2f} passes over the {n} positions of the same workload, "
-                      f"chunks of 25), FP64 NumPy oracle, {dt:.1f} s, one thread"}
+    one = {"value": done / dt, "cores": 1,
+           "sample": f"{done} patterns ({done / n:.2f} passes over the {n} positions, chunks of 25), {dt:.1f} s"}
+    workers = timing.host_workers()
+    rate, pdone, wall = timing.pool_rate(start.obj, start.probe, start.positions, I_meas, workers=workers,
+                                         budget_s=pool_s, chunk=chunk, **kw)
+    print(f"# cpu baseline: {one['value']:.1f} patterns/s on one thread, {rate:.1f} on {workers} processes",
+          file=sys.stderr, flush=True)
+    return {"value": rate, "unit": "patterns/s", "cores": workers, "kind": "oracle",
+            "sample": f"{pdone} patterns of the same workload ({n} positions split into {workers} shards, one "
+                      f"single-threaded process each, chunks of 25), FP64 NumPy oracle, {wall:.1f} s wall",
+            "single_thread": one,
+            "host_cpu": _host_cpu()}
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 WORKLOADS = {
