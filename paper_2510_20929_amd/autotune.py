@@ -55,9 +55,9 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE) -> None:
 def plan_candidates(N: int, M: int, S: int) -> List[dict]:
     cus = _cus()
     out = []
-    variants = [0, 1, 2, 3, 4] if N in (64, 128) else [0]
+    variants = [0, 1, 2, 3, 4] if N in (64, 128) else [0, 1]
     recomputes = [0, 1] if (M > 1 or S > 1) else [0]
-    grids = [0, 2 * cus] if N <= 128 else [0, cus if N == 256 else 2 * cus]
+    grids = [0, 2 * cus] if N <= 128 else [0]
     for v in variants:
         for r in recomputes:
             for g in grids:

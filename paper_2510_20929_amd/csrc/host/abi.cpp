@@ -124,13 +124,15 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
                                                   d.propagation == PTYHIP_PROP_NEAR,
                                                   d.subpixel == PTYHIP_SUBPIXEL_FOURIER);
   } else {
-    p->threads = 256;
+    p->threads = fused_big_threads(N, p->tune.variant);
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
     p->big_fused_ready = S == 1;
   }
-  // persistent grid: one workgroup per CU (the on-chip kernel fills a CU's LDS); two
-  // for 256^2 frames, whose LDS tiles leave room for a second workgroup
-  int grid = p->tune.grid > 0 ? p->tune.grid : (N == 256 ? 2 * p->cus : p->cus);
+  // persistent grid: one workgroup per CU (the on-chip frame or the line blocks of the
+  // four-step transforms fill most of a CU's LDS), two for the four-step layout with
+  // half-size blocks
+  const int per_cu = p->on_chip ? 1 : fused_big_wg_per_cu(p->tune.variant);
+  int grid = p->tune.grid > 0 ? p->tune.grid : per_cu * p->cus;
   p->grid = grid;
   if (p->scratch_stride > 0) {
     if ((st = dalloc(p, &p->scratch, p->scratch_stride * size_t(grid))) != PTYHIP_OK) return st;
@@ -333,7 +335,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
     c.gpstage = staged ? p->gpstage : nullptr;
     timing_begin(p, st);
     hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, p->grid, st)
-                              : launch_fused_big(c, N, p->grid, st);
+                              : launch_fused_big(c, N, p->tune.variant, p->grid, st);
     timing_end(p, st);
     if (e != hipSuccess) return PTYHIP_EHIP;
     if (want_obj) {
@@ -453,8 +455,8 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > 4 || tune->grid < 0 || tune->plain_chunk < 0 ||
-               tune->recompute < 0))
+  if (tune && (tune->variant < 0 || tune->variant > (desc->frame <= 128 ? 4 : 1) || tune->grid < 0 ||
+               tune->plain_chunk < 0 || tune->recompute < 0))
     return PTYHIP_EINVAL;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return PTYHIP_ENOMEM;

@@ -1,21 +1,29 @@
 // Fused forward + adjoint kernels for 256^2 and 512^2 frames (thin wrappers over
-// big_body, 256 threads per workgroup) and the probe-gradient reduction.
+// big_body) and the probe-gradient reduction. Two layouts: variant 0 runs one
+// workgroup per CU (1024 threads for 256^2, 512 for 512^2) whose line blocks fill most
+// of the LDS; variant 1 runs two workgroups per CU with half the threads and half the
+// block, so that one workgroup's loads and stores overlap the other's transforms.
 #include "big_body.hpp"
 #include "launch.hpp"
 
 namespace ptyhip {
 
-constexpr int BIG_T = 256;
+int fused_big_threads(int N, int variant) {
+  const int t = N == 256 ? 1024 : 512;
+  return variant == 1 ? t / 2 : t;
+}
+
+int fused_big_wg_per_cu(int variant) { return variant == 1 ? 2 : 1; }
 
 size_t fused_big_scratch_elems(int N, int S, int M, int E, size_t* pacc_off) {
   (void)S;
   return big_scratch_elems(N, M, E, pacc_off);
 }
 
-template <int N, int LOSS>
-__global__ __launch_bounds__(BIG_T) void fused_big_kernel(CallArgs a) {
-  __shared__ BigShared<N, BIG_T> sh;
-  big_body<N, BIG_T, LOSS>(a, sh, blockIdx.x, gridDim.x);
+template <int N, int T, int LOSS>
+__global__ __launch_bounds__(T) void fused_big_kernel(CallArgs a) {
+  __shared__ BigShared<N, T> sh;
+  big_body<N, T, LOSS>(a, sh, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void probe_reduce_big_kernel(const float2* __restrict__ scratch, size_t stride,
@@ -101,18 +109,19 @@ hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* 
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, int T>
 static hipError_t launch_big_t(const CallArgs& a, int grid, hipStream_t st) {
-  if (a.loss == 0) hipLaunchKernelGGL((fused_big_kernel<N, 0>), dim3(grid), dim3(BIG_T), 0, st, a);
-  else hipLaunchKernelGGL((fused_big_kernel<N, 1>), dim3(grid), dim3(BIG_T), 0, st, a);
+  if (a.loss == 0) hipLaunchKernelGGL((fused_big_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
+  else hipLaunchKernelGGL((fused_big_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_big(const CallArgs& a, int N, int grid, hipStream_t st) {
+hipError_t launch_fused_big(const CallArgs& a, int N, int variant, int grid, hipStream_t st) {
   if (a.S != 1) return hipErrorNotSupported;
+  const bool two = variant == 1;
   switch (N) {
-    case 256: return launch_big_t<256>(a, grid, st);
-    case 512: return launch_big_t<512>(a, grid, st);
+    case 256: return two ? launch_big_t<256, 512>(a, grid, st) : launch_big_t<256, 1024>(a, grid, st);
+    case 512: return two ? launch_big_t<512, 256>(a, grid, st) : launch_big_t<512, 512>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -14,7 +14,7 @@ def _needs_gpu():
     torch_cuda()
 
 
-@pytest.mark.parametrize("N,M,E,S", [(64, 2, 1, 1), (128, 1, 3, 1), (32, 2, 1, 3)])
+@pytest.mark.parametrize("N,M,E,S", [(64, 2, 1, 1), (128, 1, 3, 1), (32, 2, 1, 3), (256, 3, 2, 1)])
 def test_apply_A_AH(N, M, E, S):
     torch = torch_cuda()
     from paper_2510_20929_amd import Plan

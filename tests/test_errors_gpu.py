@@ -17,14 +17,15 @@ def _needs_gpu():
 
 @pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
 @pytest.mark.parametrize("kind", ["bounds", "nan_position", "nan_data"])
-def test_bad_position_is_dropped_and_latched(kind, plain):
+@pytest.mark.parametrize("N", [64, 256])
+def test_bad_position_is_dropped_and_latched(N, kind, plain):
     from paper_2510_20929_amd import FLAG_BOUNDS, FLAG_NONFINITE, Plan
-    p, I = custom_problem(41, 64, 2, 1, 1, 192, 30)
+    p, I = custom_problem(41, N, 2, 1, 1, 3 * N, 30 if N <= 128 else 12)
     bad = 7
     pos = p.positions.copy()
     I = I.copy()
     if kind == "bounds":
-        pos[bad] = (190.5, 3.0)
+        pos[bad] = (3 * N - 1.5, 3.0)
         expect = FLAG_BOUNDS
     elif kind == "nan_position":
         pos[bad, 1] = np.nan

@@ -5,7 +5,8 @@ several persistent rounds (K > number of workgroups) with a ragged tail."""
 import numpy as np
 import pytest
 
-from gpu_util import case, compare, custom_problem, run_gpu, run_oracle, torch_cuda
+import oracle
+from gpu_util import case, compare, custom_problem, dev, run_gpu, run_oracle, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +45,7 @@ def test_config1_reduced(plain):
     assert got["flags"] == 0
 
 
-@pytest.mark.parametrize("N,M,E", [(16, 1, 1), (32, 2, 3), (64, 3, 2), (128, 1, 4)])
+@pytest.mark.parametrize("N,M,E", [(16, 1, 1), (32, 2, 3), (64, 3, 2), (128, 1, 4), (256, 3, 2)])
 @pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
 def test_opr_and_modes(N, M, E, plain):
     """Eigenprobes with per-position weights, several modes, every gradient."""
@@ -87,6 +88,25 @@ def test_frame512(plain):
     compare(got, ref, grads, tag=f"N=512 {'plain' if plain else 'fused'}")
 
 
+@pytest.mark.parametrize("N,M,E", [(64, 2, 1), (256, 1, 3), (256, 3, 1), (512, 2, 1)])
+def test_forward_only(N, M, E):
+    """The forward call alone (loss and predicted intensities; no adjoint) against the
+    oracle, on the on-chip and the four-step frames, one and several modes."""
+    torch = torch_cuda()
+    start, I = custom_problem(300 + N + M + E, N, M, E, 1, N * 2 + 40, 12, loss="poisson" if M > 1 else "amplitude",
+                              weights="opr" if E > 1 else None)
+    plan = _plan(start)
+    w = None if start.weights is None else dev(start.weights)
+    ipred = torch.zeros((start.K, N, N), dtype=torch.float32, device="cuda")
+    loss = plan.forward(dev(start.obj), dev(start.probe), dev(start.positions), dev(I), weights=w, I_pred=ipred)
+    torch.cuda.synchronize()
+    ref_l, ref_I = oracle.forward(start.obj, start.probe, start.positions, I, weights=start.weights, loss=start.loss,
+                                  eps=start.eps)
+    got = {"loss": float(loss.cpu()[0]), "I_pred": ipred.cpu().numpy()}
+    compare(got, {"loss": ref_l, "I_pred": ref_I}, (), tag=f"forward N={N} M={M} E={E}")
+    assert plan.get_error() == 0
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("recompute", [0, 1])
 @pytest.mark.parametrize("N", [64, 128])
@@ -99,6 +119,22 @@ def test_fused_variants(N, variant, recompute):
     ref = run_oracle(start, I, grads)
     got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute}), start, I, grads)
     compare(got, ref, grads, tag=f"N={N} variant={variant} recompute={recompute}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("N,E", [(256, 2), (512, 1)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fourstep_layouts(N, E, variant):
+    """Both layouts of the four-step fused kernel (one or two workgroups per CU), on a
+    grid of 16 workgroups so that 40 positions take several persistent rounds with a
+    ragged tail; staged eigenprobe gradients (E = 2) and per-workgroup accumulation
+    (per-position amplitudes, E = 1)."""
+    start, I = custom_problem(900 + N + E + variant, N, 2, E, 1, N * 2 + 60, 40, loss="poisson",
+                              weights="opr" if E > 1 else "amp")
+    grads = ("obj", "probe", "pos", "weights")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "grid": 16}), start, I, grads)
+    compare(got, ref, grads, tag=f"four-step N={N} E={E} variant={variant}")
     assert got["flags"] == 0
 
 
