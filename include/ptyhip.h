@@ -101,7 +101,9 @@ typedef struct {
   int32_t n_modes;      /* M: 1..64 incoherent probe modes (Sec. 2.1) */
   int32_t n_eig;        /* E: 1..16 eigenprobes (OPR, Sec. 2.1); 1 = none */
   int32_t n_slices;     /* S: 1..64 multislice slices (Sec. 2.1) */
-  int32_t obj_h, obj_w; /* object size per slice, >= N each */
+  int32_t obj_h, obj_w; /* object size per slice, >= N each, <= 2^20 each, at most 4e9 pixels
+                           over all slices; for N >= 256 also (N + 1) * obj_w * 8 < 2^31
+                           (byte span of a patch window); otherwise PTYHIP_ESHAPE */
   int32_t loss;         /* ptyhip_loss */
   float poisson_eps;    /* eps of the Poisson loss, photons (>= 0) */
   float lambda_z;       /* slice spacing times wavelength, px^2 (used when S > 1) */

@@ -198,6 +198,8 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
   if (d->obj_h < d->frame || d->obj_w < d->frame) return PTYHIP_ESHAPE;
   if (d->obj_h > (1 << 20) || d->obj_w > (1 << 20)) return PTYHIP_ESHAPE;
   if (double(d->obj_h) * d->obj_w * d->n_slices > 4.0e9) return PTYHIP_ESHAPE;
+  // the four-step kernel addresses a patch window with 32-bit byte offsets
+  if (d->frame > 128 && (double(d->frame) + 1.0) * d->obj_w * 8.0 >= 2147483648.0) return PTYHIP_ESHAPE;
   if (!std::isfinite(d->poisson_eps) || d->poisson_eps < 0.f) return PTYHIP_ENONFINITE;
   if (!std::isfinite(d->lambda_z)) return PTYHIP_ENONFINITE;
   if (!std::isfinite(d->norm_count)) return PTYHIP_ENONFINITE;

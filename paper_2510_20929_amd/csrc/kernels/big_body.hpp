@@ -68,11 +68,31 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   using B = Big<N, TT>;
   constexpr int T = B::T, NN = B::NN, RB = B::RB, RP = B::RP, CP = B::CP, WN = B::WN, NB = B::NB;
   constexpr int NW = T / WAVE;
+  constexpr int N1 = Split<N>::N1;
+  // Every element loop over a line block has the same fixed trip count per thread (PER),
+  // so it is unrolled and its global loads are issued together; loops whose elements
+  // need several loads (eigenprobes, patch taps) go in batches of BAT pixels.
+  constexpr int PER = RB * N / T;
+  constexpr int BAT = PER < 8 ? PER : 8;
+  static_assert(PER * T == RB * N && PER % BAT == 0 && RB * N1 == T, "line blocks must split evenly");
+  // Element j of a thread: in a row block, frame pixel rb RB N + tid + j T (row RR(j) +
+  // tid / N, column tid % N when T >= N); in a column block, pixel (tid / RB + j N1) N +
+  // cb RB + tid % RB. The thread part is a vector offset, the rest a scalar offset, so
+  // the unrolled loads need no per-element address registers.
+  constexpr int RRJ = T >= N ? T / N : 0;
+  const auto rrj = [](int j) { return T >= N ? j * RRJ : (j * T) / N; };
+  const auto rcj = [](int j) { return T >= N ? 0 : (j * T) % N; };
+  const int tid = threadIdx.x;
+  const int v_row = tid * 8;
+  const int v_col = ((tid / RB) * N + tid % RB) * 8;
+  const int pix_col0 = (tid / RB) * N + tid % RB;
   float2* tile = sh.tile;
+  float2* t_row = tile + (T >= N ? (tid / N) * RP + tid % N : tid);
+  const auto tro = [](int j) { return T >= N ? j * RRJ * RP : (j * T) / N * RP + (j * T) % N; };
+  float2* t_col = tile + (tid / RB) * CP + tid % RB;
   double* red = sh.red;
   float* wsh = sh.wsh;
   double* wacc = sh.wacc;
-  const int tid = threadIdx.x;
   const float inv_n = 1.f / float(N);
   const bool fwd = a.mode != MODE_APPLY_AH;
   const bool fa = a.mode == MODE_FWD_ADJ;
@@ -85,8 +105,30 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   float2* Ps = G + NN;
   float* cf = reinterpret_cast<float*>(M > 1 ? Ps + size_t(M - 1) * NN : G);
   float2* pacc = scr + a.pacc_off;
+  const BufFrame fr(Fr, NN * 8);
+  const BufFrame gb(G, NN * 8);
+  const BufFrame cfb(cf, NN * 4);
+  const int v_win = (T >= N ? (tid / N) * a.W + tid % N : tid) * 8;
   if ((a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH) && a.zero_acc && want_probe && !a.gpstage)
     for (size_t i = tid; i < size_t(a.E) * M * NN; i += T) pacc[i] = make_float2(0.f, 0.f);
+
+  // line-block copies between the work frame and the LDS tile
+  const auto rows_to_frame = [&](int rb) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) fr.st(t_row[tro(j)], v_row, (rb * RB * N + j * T) * 8);
+  };
+  const auto frame_to_rows = [&](int rb) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) t_row[tro(j)] = fr.ld(v_row, (rb * RB * N + j * T) * 8);
+  };
+  const auto cols_to_frame = [&](int cb) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) fr.st(t_col[j * N1 * CP], v_col, (cb * RB + j * N1 * N) * 8);
+  };
+  const auto frame_to_cols = [&](int cb) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) t_col[j * N1 * CP] = fr.ld(v_col, (cb * RB + j * N1 * N) * 8);
+  };
 
   for (int k = wg; k < a.K; k += nwg) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -114,6 +156,48 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
 
+    // bilinear patch taps through a buffer over the (N+1) x (N+1) window; a tap of zero
+    // weight re-reads the base pixel
+    const BufFrame win(a.obj + size_t(p.y0) * a.W + p.x0, uint32_t((N * a.W + N + 1) * 8));
+    const int wdx = p.fx > 0.f ? 8 : 0, wdy = p.fy > 0.f ? a.W * 8 : 0;
+    const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
+    const float w10 = p.fy * (1.f - p.fx), w11 = p.fy * p.fx;
+    const auto patch = [&](int rb, int j) {
+      const int so = ((rb * RB + rrj(j)) * a.W + rcj(j)) * 8;
+      const float2 t00 = win.ld(v_win, so), t01 = win.ld(v_win, so + wdx);
+      const float2 t10 = win.ld(v_win, so + wdy), t11 = win.ld(v_win, so + wdy + wdx);
+      float2 v;
+      v.x = w00 * t00.x + w01 * t01.x + w10 * t10.x + w11 * t11.x;
+      v.y = w00 * t00.y + w01 * t01.y + w10 * t10.y + w11 * t11.y;
+      return v;
+    };
+    // probe P_m of this position at the BAT elements b0.. of row block rb, eigenprobe by
+    // eigenprobe so that the BAT loads of one eigenprobe are in flight together;
+    // `each(e, u)` sees every eigenprobe's values
+    const auto probe_batch = [&](int m, int rb, int b0, float2 (&P)[BAT], auto&& each) {
+      if (wk == nullptr) {
+        const BufFrame ub(a.probe + size_t(m) * NN, NN * 8);
+#pragma unroll
+        for (int j = 0; j < BAT; ++j) P[j] = ub.ld(v_row, (rb * RB * N + (b0 + j) * T) * 8);
+        return;
+      }
+#pragma unroll
+      for (int j = 0; j < BAT; ++j) P[j] = make_float2(0.f, 0.f);
+      for (int e = 0; e < a.E; ++e) {
+        const BufFrame ub(a.probe + (size_t(e) * M + m) * NN, NN * 8);
+        const float we = wk[e];
+        float2 u[BAT];
+#pragma unroll
+        for (int j = 0; j < BAT; ++j) u[j] = ub.ld(v_row, (rb * RB * N + (b0 + j) * T) * 8);
+#pragma unroll
+        for (int j = 0; j < BAT; ++j) {
+          P[j].x = fmaf(we, u[j].x, P[j].x);
+          P[j].y = fmaf(we, u[j].y, P[j].y);
+        }
+        each(e, u);
+      }
+    };
+
     if (fwd) {
       double lsum = 0.0;
       const float* im = a.imeas ? a.imeas + size_t(k) * NN : nullptr;
@@ -121,41 +205,63 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         const bool last = m == M - 1;
         // row transforms of the exit wave P_m o
         for (int rb = 0; rb < NB; ++rb) {
-          for (int i = tid; i < RB * N; i += T) {
-            const int r = i / N, x = i % N, y = rb * RB + r;
-            tile[r * RP + x] = cmul(probe_at(a.probe, wk, a.E, M, NN, m, y * N + x), bilinear(a.obj, a.W, p, y, x));
+          for (int b0 = 0; b0 < PER; b0 += BAT) {
+            float2 P[BAT];
+            probe_batch(m, rb, b0, P, [](int, const float2(&)[BAT]) {});
+#pragma unroll
+            for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
           }
           __syncthreads();
           LineTile<N, RB, T>::template run<false>(tile, RP, 1, a.tw);
           __syncthreads();
-          for (int i = tid; i < RB * N; i += T) Fr[(rb * RB + i / N) * N + (i % N)] = tile[(i / N) * RP + (i % N)];
+          rows_to_frame(rb);
           __syncthreads();
         }
         // column transforms: far field and intensity; the last mode also the loss, dl/dI
         // and (forward + adjoint) its own inverse column transforms
         for (int cb = 0; cb < NB; ++cb) {
-          for (int i = tid; i < N * RB; i += T) tile[(i / RB) * CP + (i % RB)] = Fr[(i / RB) * N + cb * RB + (i % RB)];
+          frame_to_cols(cb);
           __syncthreads();
           LineTile<N, RB, T>::template run<false>(tile, 1, CP, a.tw);
           __syncthreads();
-          for (int i = tid; i < N * RB; i += T) {
-            const int ky = i / RB, kx = cb * RB + (i % RB), pix = ky * N + kx, ti = ky * CP + (i % RB);
-            const float2 v = cscale(tile[ti], inv_n);
-            if (a.mode == MODE_APPLY_A) {
-              a.psi_out[(size_t(k) * M + m) * NN + pix] = v;
-            } else if (!last) {
-              if (fa) Ps[size_t(m) * NN + pix] = v;
-              cf[pix] = (m == 0 ? 0.f : cf[pix]) + cabs2(v);
-            } else {
-              const float I = (m == 0 ? 0.f : cf[pix]) + cabs2(v);
-              const int ci = centred_index(ky, kx, N);
-              float l, c;
-              loss_terms<LOSS>(I, im[ci], a.eps, l, c);
-              if (a.ipred) a.ipred[size_t(k) * NN + ci] = I;
-              lsum += double(l);
-              if (fa) {
-                if (M > 1) cf[pix] = c;
-                tile[ti] = cscale(v, a.gscale * c);
+          if (a.mode == MODE_APPLY_A) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+              a.psi_out[(size_t(k) * M + m) * NN + pix_col0 + cb * RB + j * N1 * N] = cscale(t_col[j * N1 * CP], inv_n);
+          } else if (!last) {
+            const BufFrame pb(Ps + size_t(m) * NN, NN * 8);
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+              const int so = cb * RB + j * N1 * N;
+              const float2 v = cscale(t_col[j * N1 * CP], inv_n);
+              if (fa) pb.st(v, v_col, so * 8);
+              cfb.stf((m == 0 ? 0.f : cfb.ldf(v_col / 2, so * 4)) + cabs2(v), v_col / 2, so * 4);
+            }
+          } else {
+            const BufFrame imb(im, NN * 4);
+            for (int b0 = 0; b0 < PER; b0 += BAT) {
+              float imv[BAT], cfv[BAT];
+              int ci[BAT];
+#pragma unroll
+              for (int j = 0; j < BAT; ++j) {
+                const int ky = tid / RB + (b0 + j) * N1, kx = cb * RB + tid % RB;
+                ci[j] = centred_index(ky, kx, N);
+                imv[j] = imb.ldf(ci[j] * 4, 0);
+                cfv[j] = m == 0 ? 0.f : cfb.ldf(v_col / 2, (cb * RB + (b0 + j) * N1 * N) * 4);
+              }
+#pragma unroll
+              for (int j = 0; j < BAT; ++j) {
+                float2& tv = t_col[(b0 + j) * N1 * CP];
+                const float2 v = cscale(tv, inv_n);
+                const float I = cfv[j] + cabs2(v);
+                float l, c;
+                loss_terms<LOSS>(I, imv[j], a.eps, l, c);
+                if (a.ipred) a.ipred[size_t(k) * NN + ci[j]] = I;
+                lsum += double(l);
+                if (fa) {
+                  if (M > 1) cfb.stf(c, v_col / 2, (cb * RB + (b0 + j) * N1 * N) * 4);
+                  tv = cscale(v, a.gscale * c);
+                }
               }
             }
           }
@@ -163,7 +269,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             __syncthreads();
             LineTile<N, RB, T>::template run<true>(tile, 1, CP, a.tw);
             __syncthreads();
-            for (int i = tid; i < N * RB; i += T) Fr[(i / RB) * N + cb * RB + (i % RB)] = tile[(i / RB) * CP + (i % RB)];
+            cols_to_frame(cb);
           }
           __syncthreads();
         }
@@ -191,85 +297,82 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
 
     // adjoint, one mode at a time; forward + adjoint starts with the last mode, whose
     // inverse column transforms the column pass has already done. The weight-gradient
-    // terms are summed per thread over a row block, then per wave into the wave's own
+    // terms are summed per thread over a pixel batch, then per wave into the wave's own
     // LDS slots (no atomics; the slots are added in a fixed order at the end).
     const bool want_w = (a.want & WANT_WEIGHTS) && wk != nullptr;
     const int lane = tid & (WAVE - 1), wave = tid / WAVE;
     float2* gwin = a.gwin ? a.gwin + size_t(k) * WN * WN : nullptr;
     const bool want_obj = (a.want & WANT_OBJ) && gwin != nullptr;
-    const float w00 = (1.f - p.fy) * (1.f - p.fx), w01 = (1.f - p.fy) * p.fx;
-    const float w10 = p.fy * (1.f - p.fx), w11 = p.fy * p.fx;
     double gy = 0.0, gx = 0.0;
-    for (int j = 0; j < M; ++j) {
-      const int m = fa ? (j == 0 ? M - 1 : j - 1) : j;
-      const bool first = j == 0, lastj = j == M - 1;
+    for (int jm = 0; jm < M; ++jm) {
+      const int m = fa ? (jm == 0 ? M - 1 : jm - 1) : jm;
+      const bool first = jm == 0, lastj = jm == M - 1;
       if (!(fa && first)) {
         // inverse column transforms of the scaled far field (or of the given far field)
+        const BufFrame src(fa ? Ps + size_t(m) * NN : a.Y + (size_t(k) * M + m) * NN, NN * 8);
         for (int cb = 0; cb < NB; ++cb) {
-          for (int i = tid; i < N * RB; i += T) {
-            const int pix = (i / RB) * N + cb * RB + (i % RB);
-            tile[(i / RB) * CP + (i % RB)] = fa ? cscale(Ps[size_t(m) * NN + pix], a.gscale * cf[pix])
-                                                : a.Y[(size_t(k) * M + m) * NN + pix];
+#pragma unroll
+          for (int j = 0; j < PER; ++j) {
+            const int so = cb * RB + j * N1 * N;
+            const float2 v = src.ld(v_col, so * 8);
+            t_col[j * N1 * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
           }
           __syncthreads();
           LineTile<N, RB, T>::template run<true>(tile, 1, CP, a.tw);
           __syncthreads();
-          for (int i = tid; i < N * RB; i += T) Fr[(i / RB) * N + cb * RB + (i % RB)] = tile[(i / RB) * CP + (i % RB)];
+          cols_to_frame(cb);
           __syncthreads();
         }
       }
       // inverse row transforms, conjugate multiplies, probe-side gradients
+      const BufFrame stage(a.gpstage ? a.gpstage + (size_t(k) * M + m) * NN : Fr, NN * 8);
       for (int rb = 0; rb < NB; ++rb) {
-        for (int i = tid; i < RB * N; i += T) tile[(i / N) * RP + (i % N)] = Fr[(rb * RB + i / N) * N + (i % N)];
+        frame_to_rows(rb);
         __syncthreads();
         LineTile<N, RB, T>::template run<true>(tile, RP, 1, a.tw);
         __syncthreads();
-        double ws[BIG_MAX_EIG];
+        for (int b0 = 0; b0 < PER; b0 += BAT) {
+          float2 g[BAT], gP[BAT], P[BAT];
 #pragma unroll
-        for (int e = 0; e < BIG_MAX_EIG; ++e) ws[e] = 0.0;
-        for (int i = tid; i < RB * N; i += T) {
-          const int r = i / N, x = i % N, pix = (rb * RB + r) * N + x;
-          const float2 g = cscale(tile[r * RP + x], inv_n);
-          const float2 gP = cmulc(bilinear(a.obj, a.W, p, rb * RB + r, x), g);
+          for (int j = 0; j < BAT; ++j) {
+            g[j] = cscale(t_row[tro(b0 + j)], inv_n);
+            gP[j] = cmulc(patch(rb, b0 + j), g[j]);
+          }
           // probe of this position and mode; each eigenprobe pixel is read once, for the
-          // probe and for the weight-gradient term Re<gP, U_e,m>
-          float2 P;
-          if (wk == nullptr) {
-            P = a.probe[size_t(m) * NN + pix];
-          } else {
-            P = make_float2(0.f, 0.f);
+          // probe and for the weight-gradient term Re<gP, U_e,m> (wave sums into the wave's
+          // LDS slot)
+          probe_batch(m, rb, b0, P, [&](int e, const float2(&u)[BAT]) {
+            if (!want_w) return;
+            double t = 0.0;
 #pragma unroll
-            for (int e = 0; e < BIG_MAX_EIG; ++e)
-              if (e < a.E) {
-                const float2 u = a.probe[(size_t(e) * M + m) * NN + pix];
-                P.x = fmaf(wk[e], u.x, P.x);
-                P.y = fmaf(wk[e], u.y, P.y);
-                if (want_w) ws[e] += double(cdotre(gP, u));
+            for (int j = 0; j < BAT; ++j) t += double(cdotre(gP[j], u[j]));
+            t = wave_sum(t);
+            if (lane == 0) sh.wred[e * NW + wave] += t;
+          });
+          float2 gprev[BAT];
+          if (!first) {
+#pragma unroll
+            for (int j = 0; j < BAT; ++j) gprev[j] = gb.ld(v_row, (rb * RB * N + (b0 + j) * T) * 8);
+          }
+#pragma unroll
+          for (int j = 0; j < BAT; ++j) {
+            const int so = rb * RB * N + (b0 + j) * T;
+            float2 go = cmulc(P[j], g[j]);
+            if (!first) go = cadd(go, gprev[j]);
+            if (!lastj) gb.st(go, v_row, so * 8);
+            t_row[tro(b0 + j)] = go;
+            if (want_probe && a.gpstage) {
+              stage.st(gP[j], v_row, so * 8);
+            } else if (want_probe) {
+              const int ne = wk ? a.E : 1;
+              for (int e = 0; e < ne; ++e) {
+                float2& acc = pacc[(size_t(e) * M + m) * NN + tid + so];
+                const float w = wk ? wk[e] : 1.f;
+                acc.x = fmaf(w, gP[j].x, acc.x);
+                acc.y = fmaf(w, gP[j].y, acc.y);
               }
-          }
-          float2 go = cmulc(P, g);
-          if (!first) go = cadd(go, G[pix]);
-          if (!lastj) G[pix] = go;
-          tile[r * RP + x] = go;
-          if (want_probe && a.gpstage) {
-            a.gpstage[(size_t(k) * M + m) * NN + pix] = gP;
-          } else if (want_probe) {
-            const int ne = wk ? a.E : 1;
-            for (int e = 0; e < ne; ++e) {
-              float2& acc = pacc[(size_t(e) * M + m) * NN + pix];
-              const float w = wk ? wk[e] : 1.f;
-              acc.x = fmaf(w, gP.x, acc.x);
-              acc.y = fmaf(w, gP.y, acc.y);
             }
           }
-        }
-        if (want_w) {
-#pragma unroll
-          for (int e = 0; e < BIG_MAX_EIG; ++e)
-            if (e < a.E) {
-              const double t = wave_sum(ws[e]);
-              if (lane == 0) sh.wred[e * NW + wave] += t;
-            }
         }
         if (lastj && (want_obj || want_pos)) {
           // window rows of this block (and the bottom row N after the last block): the
@@ -282,12 +385,12 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           for (int idx = tid; idx < rows * WN; idx += T) {
             const int ry = idx / WN, px = idx - ry * WN, py = rb * RB + ry;
             const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
-            const float2* rc = tile + ry * RP;
-            const float2* rp = ry > 0 ? tile + (ry - 1) * RP : prev;
-            const float2 g00 = (iy0 && ix0) ? rc[px] : z;
-            const float2 g01 = (iy0 && ix1) ? rc[px - 1] : z;
-            const float2 g10 = (iy1 && ix0) ? rp[px] : z;
-            const float2 g11 = (iy1 && ix1) ? rp[px - 1] : z;
+            const float2* rcur = tile + ry * RP;
+            const float2* rabove = ry > 0 ? tile + (ry - 1) * RP : prev;
+            const float2 g00 = (iy0 && ix0) ? rcur[px] : z;
+            const float2 g01 = (iy0 && ix1) ? rcur[px - 1] : z;
+            const float2 g10 = (iy1 && ix0) ? rabove[px] : z;
+            const float2 g11 = (iy1 && ix1) ? rabove[px - 1] : z;
             if (want_obj) {
               float2 g;
               g.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;

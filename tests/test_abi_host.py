@@ -49,6 +49,8 @@ def test_exports_every_declared_symbol():
     (dict(frame=64, n_slices=3, obj_h=200, obj_w=200, subpixel="fourier"), 7), # one slice,
     (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=5.0, subpixel="fourier"), 7),  # far field
     (dict(frame=64, obj_h=200, obj_w=200, subpixel=3), 1),
+    (dict(frame=512, obj_h=600, obj_w=600000), 2),                           # window span over 2^31 bytes
+    (dict(frame=128, obj_h=600, obj_w=600000), 0),
 ])
 def test_desc_validate(kw, status):
     mod = _lib()
