@@ -306,15 +306,20 @@ struct LineTile {
   static constexpr int LPR = T / N1;               // lines per round
   static_assert(NL % LPR == 0, "lines must fill whole rounds");
   static constexpr int ROUNDS = NL / LPR;
+  // Position of the intermediate element (n1, k2) inside a line: N1 k2 + (n1 ^ (k2 mod
+  // N1)). The XOR spreads the N1 lanes of a line over distinct LDS banks both where
+  // stage 1 writes (fixed k2, lanes n1) and where stage 2 reads (fixed n1, lanes k2),
+  // which in natural order would all hit one bank.
+  __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ (k2 & (N1 - 1))); }
 
   // In-place transform of all NL lines. Caller syncs before (data in LDS) and after.
   template <bool INV>
   __device__ __forceinline__ static void run(float2* lds, int LS, int ES, const float2* __restrict__ tw_) {
     const int t = opaque_tid();
-    const float2* __restrict__ tw = opaque_ptr(tw_);
+    const float2* __restrict__ tw = tw_;
     const int q = t % N1, lr = t / N1;
     if constexpr (!INV) {
-      // stage 1 in place: x[n1 + N1 n2] -> Y[n1][k2] stored at n1 + N1 k2
+      // stage 1 in place: x[n1 + N1 n2] -> Y[n1][k2] stored at sw(n1, k2)
 #pragma unroll 1
       for (int r = 0; r < ROUNDS; ++r) {
         float2* base = lds + (lr + LPR * r) * LS;
@@ -325,7 +330,7 @@ struct LineTile {
 #pragma unroll
         for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul(u[k2], tw[q * k2]);
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) base[(q + N1 * k2) * ES] = u[k2];
+        for (int k2 = 0; k2 < N2; ++k2) base[sw(q, k2) * ES] = u[k2];
       }
       __syncthreads();
       float2 w[ROUNDS][N2];
@@ -337,7 +342,7 @@ struct LineTile {
           const int k2 = q + N1 * jj;
           float2* u = &w[r][jj * N1];
 #pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1) u[n1] = base[(n1 + N1 * k2) * ES];
+          for (int n1 = 0; n1 < N1; ++n1) u[n1] = base[sw(n1, k2) * ES];
           Dft<N1, false>::run(u);
         }
       }
@@ -371,7 +376,7 @@ struct LineTile {
         for (int jj = 0; jj < N2 / N1; ++jj) {
           const int k2 = q + N1 * jj;
 #pragma unroll
-          for (int n1 = 0; n1 < N1; ++n1) base[(n1 + N1 * k2) * ES] = w[r][jj * N1 + n1];
+          for (int n1 = 0; n1 < N1; ++n1) base[sw(n1, k2) * ES] = w[r][jj * N1 + n1];
         }
       }
       __syncthreads();
@@ -380,7 +385,7 @@ struct LineTile {
         float2* base = lds + (lr + LPR * r) * LS;
         float2 u[N2];
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) u[k2] = base[(q + N1 * k2) * ES];
+        for (int k2 = 0; k2 < N2; ++k2) u[k2] = base[sw(q, k2) * ES];
 #pragma unroll
         for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul_conjb(u[k2], tw[q * k2]);
         Dft<N2, true>::run(u);

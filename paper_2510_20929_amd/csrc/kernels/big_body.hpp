@@ -47,6 +47,7 @@ template <int N, int TT>
 struct BigShared {
   float2 tile[Big<N, TT>::LDS];
   float2 prevg[2][N];  // last patch-gradient row of the previous row block (double-buffered)
+  float2 tw[N];        // twiddle table W_N^i of the line transforms
   double red[2 * (TT / WAVE)];
   double wred[BIG_MAX_EIG * (TT / WAVE)];
   float wsh[BIG_MAX_EIG];
@@ -111,6 +112,9 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   const int v_win = (T >= N ? (tid / N) * a.W + tid % N : tid) * 8;
   if ((a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH) && a.zero_acc && want_probe && !a.gpstage)
     for (size_t i = tid; i < size_t(a.E) * M * NN; i += T) pacc[i] = make_float2(0.f, 0.f);
+  float2* tws = sh.tw;
+  for (int i = tid; i < N; i += T) tws[i] = a.tw[i];
+  __syncthreads();
 
   // line-block copies between the work frame and the LDS tile
   const auto rows_to_frame = [&](int rb) {
@@ -212,7 +216,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
           }
           __syncthreads();
-          LineTile<N, RB, T>::template run<false>(tile, RP, 1, a.tw);
+          LineTile<N, RB, T>::template run<false>(tile, RP, 1, tws);
           __syncthreads();
           rows_to_frame(rb);
           __syncthreads();
@@ -222,7 +226,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         for (int cb = 0; cb < NB; ++cb) {
           frame_to_cols(cb);
           __syncthreads();
-          LineTile<N, RB, T>::template run<false>(tile, 1, CP, a.tw);
+          LineTile<N, RB, T>::template run<false>(tile, 1, CP, tws);
           __syncthreads();
           if (a.mode == MODE_APPLY_A) {
 #pragma unroll
@@ -267,7 +271,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           }
           if (fa && last) {
             __syncthreads();
-            LineTile<N, RB, T>::template run<true>(tile, 1, CP, a.tw);
+            LineTile<N, RB, T>::template run<true>(tile, 1, CP, tws);
             __syncthreads();
             cols_to_frame(cb);
           }
@@ -318,7 +322,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             t_col[j * N1 * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
           }
           __syncthreads();
-          LineTile<N, RB, T>::template run<true>(tile, 1, CP, a.tw);
+          LineTile<N, RB, T>::template run<true>(tile, 1, CP, tws);
           __syncthreads();
           cols_to_frame(cb);
           __syncthreads();
@@ -329,7 +333,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       for (int rb = 0; rb < NB; ++rb) {
         frame_to_rows(rb);
         __syncthreads();
-        LineTile<N, RB, T>::template run<true>(tile, RP, 1, a.tw);
+        LineTile<N, RB, T>::template run<true>(tile, RP, 1, tws);
         __syncthreads();
         for (int b0 = 0; b0 < PER; b0 += BAT) {
           float2 g[BAT], gP[BAT], P[BAT];
