@@ -245,8 +245,8 @@ ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);
 /* Clear the latch (asynchronously on `stream`). */
 ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
 
-/* Many independent reconstructions of uneven frame sizes in one persistent launch,
- * captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
+/* Many independent reconstructions of uneven frame sizes in one persistent launch per
+ * frame-size class (64^2/128^2, 256^2, 512^2), captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
  * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. */
 ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, int32_t n, const ptyhip_tune* tune,
                                   ptyhip_batch* out);
@@ -256,8 +256,9 @@ ptyhip_status ptyhip_batch_bind(ptyhip_batch b, int32_t i, const float* obj, con
                                 const float* weights, const float* positions, const float* I_meas, double* loss,
                                 float* g_obj, float* g_probe, float* g_pos, float* g_weights);
 /* Run every dataset (gradient flags as in ptyhip_forward_adjoint; outputs are
- * overwritten). By default all datasets run in one persistent launch whose workgroups
- * are split among the datasets in proportion to their work, followed by per-dataset
+ * overwritten). By default the datasets of each frame-size class run in one persistent
+ * launch (one workgroup per CU, or the tuned grid) whose workgroups are split among
+ * them in proportion to their work, followed by per-dataset
  * reductions; the first launch with given flags captures this into a hipGraph on
  * `stream` and later launches replay it. PTYHIP_BATCH_PER_CALL runs one non-captured
  * fused call per dataset instead, PTYHIP_PLAIN one per-step call per dataset. Frame

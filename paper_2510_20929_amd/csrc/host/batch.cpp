@@ -1,5 +1,5 @@
-// Batched uneven reconstructions: many independent datasets in one persistent launch,
-// captured once into a hipGraph and replayed.
+// Batched uneven reconstructions: many independent datasets in one persistent launch
+// per frame-size class, captured once into a hipGraph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +29,9 @@ struct Bound {
 struct ptyhip_batch_s {
   int n = 0;
   int device = 0;
-  int total_wg = 0;
+  int cls_first[BATCH_CLASSES] = {0, 0, 0};  // table entries of each class (sorted table)
+  int cls_count[BATCH_CLASSES] = {0, 0, 0};
+  int cls_wg[BATCH_CLASSES] = {0, 0, 0};     // workgroups of each class's launch
   std::vector<Plan*> plans;
   std::vector<int> K, first_wg, n_wg;
   std::vector<Bound> bound;
@@ -79,39 +81,50 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     delete b;
     return PTYHIP_EHIP;
   }
-  b->total_wg = std::max(n, (tune && tune->grid > 0) ? int(tune->grid) : prop.multiProcessorCount);
   // work of each dataset: positions x modes x (N^2 log2 N^2) transform cost
   std::vector<double> cost(n);
   for (int i = 0; i < n; ++i) {
     const double N = descs[i].frame;
     cost[i] = double(std::max(K[i], 1)) * descs[i].n_modes * N * N * std::log2(N * N);
   }
-  const double tot = std::accumulate(cost.begin(), cost.end(), 0.0);
-  // one workgroup each, the rest by largest remainder in proportion to the work
+  // per frame-size class: one workgroup per CU (a tuned total if given), one workgroup per
+  // dataset at least, the rest by largest remainder in proportion to the work; inside a
+  // class the most expensive datasets take the first workgroups
   b->n_wg.assign(n, 1);
-  int left = b->total_wg - n;
-  std::vector<double> share(n), rem(n);
-  for (int i = 0; i < n; ++i) share[i] = cost[i] / tot * left;
-  int given = 0;
-  for (int i = 0; i < n; ++i) {
-    const int w = int(std::floor(share[i]));
-    b->n_wg[i] += w;
-    given += w;
-    rem[i] = share[i] - w;
-  }
-  std::vector<int> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int x, int y) { return rem[x] > rem[y]; });
-  for (int j = 0; j < left - given; ++j) b->n_wg[order[j % n]] += 1;
-  // the most expensive datasets take the first workgroups
-  std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   b->first_wg.assign(n, 0);
-  std::vector<int> by_first(n);
-  int w0 = 0;
-  for (int j = 0; j < n; ++j) {
-    b->first_wg[order[j]] = w0;
-    w0 += b->n_wg[order[j]];
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    std::vector<int> members;
+    for (int i = 0; i < n; ++i)
+      if (batch_class(descs[i].frame) == c) members.push_back(i);
+    const int nc = int(members.size());
+    b->cls_count[c] = nc;
+    if (nc == 0) continue;
+    const int total = std::max(nc, (tune && tune->grid > 0) ? int(tune->grid) : prop.multiProcessorCount);
+    b->cls_wg[c] = total;
+    double tot = 0.0;
+    for (int i : members) tot += cost[i];
+    const int left = total - nc;
+    std::vector<double> rem(n, 0.0);
+    int given = 0;
+    for (int i : members) {
+      const double share = cost[i] / tot * left;
+      const int w = int(std::floor(share));
+      b->n_wg[i] += w;
+      given += w;
+      rem[i] = share - w;
+    }
+    std::vector<int> order = members;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return rem[x] > rem[y]; });
+    for (int j = 0; j < left - given; ++j) b->n_wg[order[j % nc]] += 1;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    int w0 = 0;
+    for (int i : order) {
+      b->first_wg[i] = w0;
+      w0 += b->n_wg[i];
+    }
   }
+  b->cls_first[0] = 0;
+  for (int c = 1; c < BATCH_CLASSES; ++c) b->cls_first[c] = b->cls_first[c - 1] + b->cls_count[c - 1];
   b->K.assign(K, K + n);
   b->bound.resize(n);
   b->plans.assign(n, nullptr);
@@ -124,8 +137,7 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     b->plans[i] = p;
     ptyhip_tune t{};
     if (tune) t = *tune;
-    const int def_grid = descs[i].frame == 256 ? 2 * prop.multiProcessorCount : prop.multiProcessorCount;
-    t.grid = std::max(b->n_wg[i], def_grid);
+    t.grid = std::max(b->n_wg[i], prop.multiProcessorCount);
     t.variant = 0;
     t.recompute = 0;
     if (t.plain_chunk <= 0) t.plain_chunk = 128;
@@ -136,6 +148,7 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
       return s;
     }
     // the batched launch runs the on-chip bodies with 512 threads: size its scratch for that
+    // (the four-step bodies' scratch does not depend on the thread count)
     size_t off = 0;
     const size_t need = batched_scratch_elems(descs[i].frame, descs[i].n_modes, descs[i].n_eig, &off);
     if (need > p->scratch_stride || off != p->pacc_off) {
@@ -236,10 +249,14 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
     e.N = p->d.frame;
     b->tab[i] = e;
   }
-  // the kernels find a workgroup's dataset by first_wg, so upload in first_wg order
+  // each class's kernel finds a workgroup's dataset by first_wg among the class's
+  // entries, so upload by class, then in first_wg order
   std::vector<int> order(b->n);
   std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int x, int y) { return b->first_wg[x] < b->first_wg[y]; });
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    const int cx = batch_class(b->tab[x].N), cy = batch_class(b->tab[y].N);
+    return cx != cy ? cx < cy : b->first_wg[x] < b->first_wg[y];
+  });
   std::vector<BatchEntry> sorted(b->n);
   for (int j = 0; j < b->n; ++j) sorted[j] = b->tab[order[j]];
   if (!b->uploaded || std::memcmp(sorted.data(), b->staging, sizeof(BatchEntry) * b->n) != 0) {
@@ -257,7 +274,7 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
     b->graph = nullptr;
     // capture records the launches without running them; the graph then runs on `st`
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PTYHIP_EHIP;
-    hipError_t e = launch_batched(b->dev_tab, sorted.data(), b->n, b->total_wg, b->cap);
+    hipError_t e = launch_batched(b->dev_tab, sorted.data(), b->n, b->cls_first, b->cls_count, b->cls_wg, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) return PTYHIP_EHIP;

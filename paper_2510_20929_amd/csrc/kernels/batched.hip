@@ -1,12 +1,14 @@
-// Many independent reconstructions of uneven frame size in one persistent launch.
+// Many independent reconstructions of uneven frame size in a few persistent launches.
 //
-// The launch's workgroups are partitioned among the datasets in proportion to their
-// work (positions x modes x transform cost); every workgroup reads its dataset's call
-// arguments from a device descriptor table and runs the same per-position body as
-// the per-plan kernels (512 threads: on-chip transforms for 64^2 and 128^2, scratch-
-// resident four-step transforms for 256^2 and 512^2). Gather, probe reduction and
-// final reductions follow per dataset; they too read their pointers from the table,
-// so a captured graph stays valid when the caller rebinds buffers.
+// Datasets are grouped by frame-size class (on-chip 64^2 / 128^2, four-step 256^2,
+// four-step 512^2) and each class runs as one persistent launch with that class's best
+// thread layout. A launch's workgroups are partitioned among its datasets in proportion
+// to their work (positions x modes x transform cost); every workgroup reads its
+// dataset's call arguments from a device descriptor table (sorted by class, then by
+// first workgroup) and runs the same per-position body as the per-plan kernels (512
+// threads for the on-chip frames and 512^2, 1024 for 256^2). Gather, probe reduction
+// and final reductions follow per dataset; they too read their pointers from the
+// table, so a captured graph stays valid when the caller rebinds buffers.
 #include "big_body.hpp"
 #include "gather.hpp"
 #include "launch.hpp"
@@ -16,17 +18,21 @@ namespace ptyhip {
 
 constexpr int BT = 512;
 
-union BatchShared {
+union SmallBatchShared {
   SmallShared<64, BT> s64;
   SmallShared<128, BT> s128;
-  BigShared<256, BT> b256;
-  BigShared<512, BT> b512;
 };
 
-__global__ __launch_bounds__(BT) void batched_kernel(const BatchEntry* __restrict__ tab, int n) {
-  __shared__ BatchShared sh;
+// the dataset of this workgroup within the class's entries tab[0..n)
+__device__ __forceinline__ int batch_dataset(const BatchEntry* __restrict__ tab, int n) {
   int d = 0;
   while (d + 1 < n && int(blockIdx.x) >= tab[d + 1].first_wg) ++d;
+  return d;
+}
+
+__global__ __launch_bounds__(BT) void batched_small_kernel(const BatchEntry* __restrict__ tab, int n) {
+  __shared__ SmallBatchShared sh;
+  const int d = batch_dataset(tab, n);
   const CallArgs a = tab[d].a;
   const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
   switch (tab[d].N * 2 + a.loss) {
@@ -34,13 +40,21 @@ __global__ __launch_bounds__(BT) void batched_kernel(const BatchEntry* __restric
     case 129: small_body<64, BT, 1>(a, sh.s64, wg, nwg); break;
     case 256: small_body<128, BT, 0>(a, sh.s128, wg, nwg); break;
     case 257: small_body<128, BT, 1>(a, sh.s128, wg, nwg); break;
-    case 512: big_body<256, BT, 0>(a, sh.b256, wg, nwg); break;
-    case 513: big_body<256, BT, 1>(a, sh.b256, wg, nwg); break;
-    case 1024: big_body<512, BT, 0>(a, sh.b512, wg, nwg); break;
-    case 1025: big_body<512, BT, 1>(a, sh.b512, wg, nwg); break;
     default: break;
   }
 }
+
+template <int N, int T>
+__global__ __launch_bounds__(T) void batched_big_kernel(const BatchEntry* __restrict__ tab, int n) {
+  __shared__ BigShared<N, T> sh;
+  const int d = batch_dataset(tab, n);
+  const CallArgs a = tab[d].a;
+  const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
+  if (a.loss == 0) big_body<N, T, 0>(a, sh, wg, nwg);
+  else big_body<N, T, 1>(a, sh, wg, nwg);
+}
+
+int batch_class(int N) { return N <= 128 ? 0 : (N == 256 ? 1 : 2); }
 
 size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off) {
   if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, 0, pacc_off, 0);
@@ -85,9 +99,18 @@ __global__ __launch_bounds__(1024) void batch_finalize_kernel(const BatchEntry* 
     for (int i = threadIdx.x; i < a.E * a.K; i += 1024) tab[d].g_w[i] = float(a.w_part[i]);
 }
 
-hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, int total_wg,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(batched_kernel, dim3(total_wg), dim3(BT), 0, st, dev_tab, n);
+hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
+                          const int* cls_count, const int* cls_wg, hipStream_t st) {
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    if (cls_count[c] == 0) continue;
+    const BatchEntry* t = dev_tab + cls_first[c];
+    const dim3 grid{unsigned(cls_wg[c])};
+    switch (c) {
+      case 0: hipLaunchKernelGGL(batched_small_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
+      case 1: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
+      default: hipLaunchKernelGGL((batched_big_kernel<512, 512>), grid, dim3(512), 0, st, t, cls_count[c]); break;
+    }
+  }
   for (int d = 0; d < n; ++d) {
     const BatchEntry& e = host_tab[d];
     if (e.a.mode != MODE_FWD_ADJ) continue;

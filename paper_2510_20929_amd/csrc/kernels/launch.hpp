@@ -109,7 +109,10 @@ struct BatchEntry {
 };
 
 size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off);
-hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, int total_wg,
-                          hipStream_t st);
+// frame-size classes of the batched launch: 0 = on chip (64^2, 128^2), 1 = 256^2, 2 = 512^2
+constexpr int BATCH_CLASSES = 3;
+int batch_class(int N);
+hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
+                          const int* cls_count, const int* cls_wg, hipStream_t st);
 
 }  // namespace ptyhip
