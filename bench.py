@@ -167,7 +167,7 @@ def kernel_name(plan, prob, tune):
     info = plan.info()
     loss = 1 if prob.loss == "poisson" else 0
     if prob.N >= 256:
-        return "fused_big_kernel<%d, %d>" % (prob.N, loss)
+        return "fused_big_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     if prob.S > 1:
         return "fused_small_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
