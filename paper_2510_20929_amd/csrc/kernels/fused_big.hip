@@ -69,16 +69,26 @@ __global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict
     float2 acc[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] = make_float2(0.f, 0.f);
-    for (int kk = k0; kk < k1; ++kk) {
-      if (!valid[kk]) continue;
-      const float2 v = gp[size_t(kk) * MN + g];
-      const float* wk = w + size_t(kk) * E;
+    // four positions' loads in flight together; they are added in position order
+    for (int kk = k0; kk < k1; kk += 4) {
+      float2 v[4];
+      bool on[4];
 #pragma unroll
-      for (int e = 0; e < 16; ++e)
-        if (e < E) {
-          acc[e].x = fmaf(wk[e], v.x, acc[e].x);
-          acc[e].y = fmaf(wk[e], v.y, acc[e].y);
-        }
+      for (int u = 0; u < 4; ++u) {
+        on[u] = kk + u < k1 && valid[kk + u];
+        v[u] = on[u] ? gp[size_t(kk + u) * MN + g] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!on[u]) continue;
+        const float* wk = w + size_t(kk + u) * E;
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          if (e < E) {
+            acc[e].x = fmaf(wk[e], v[u].x, acc[e].x);
+            acc[e].y = fmaf(wk[e], v[u].y, acc[e].y);
+          }
+      }
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e)
