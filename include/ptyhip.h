@@ -123,9 +123,9 @@ typedef struct {
                            1 = 1024 (128^2) / 256 (64^2) threads; 2 = 512 threads, patch and
                            patch gradient in registers; 3 = as 2 with 1024 / 256 threads;
                            4 = as 3 with the patch gradient in scratch.
-                           Four-step fused kernel (256^2, 512^2): 0 = one workgroup per CU
-                           (1024 / 512 threads); 1 = two per CU (512 / 256 threads, half-size
-                           line blocks); other values are PTYHIP_EINVAL */
+                           Four-step fused kernel (256^2, 512^2): 0 = one workgroup of 1024
+                           threads per CU; 1 = two per CU (512 / 256 threads, smaller line
+                           blocks); other values are PTYHIP_EINVAL */
   int32_t grid;         /* persistent workgroups; 0 = occupancy x compute units */
   int32_t recompute;    /* 1 = recompute (multislice: incident waves; several modes: far fields)
                            instead of keeping them in workgroup scratch */

@@ -396,4 +396,84 @@ struct LineTile {
   }
 };
 
+// ----------------------------------------------------------------------------- wide line tiles
+// As LineTile, but each line of N = N1 N2 points is served by N1 = 2 N2 threads, so that
+// T threads cover T / N1 lines per round with only N2 elements each (for 512 points,
+// 1024 threads cover 32 lines, a block that fits the LDS). Stage 1 is unchanged: thread
+// n1 runs a register DFT of size N2 over x[n1 + N1 n2] and applies W_N^{n1 k2}. Stage 2
+// needs one DFT of size N1 per k2, shared by the adjacent threads (2 k2, 2 k2 + 1): by
+// decimation in frequency, the even outputs are the DFT of size N2 of Y[n] + Y[n + N2]
+// and the odd outputs the DFT of size N2 of (Y[n] - Y[n + N2]) W_N1^n, one half per
+// thread. The inverse runs the adjoint: each thread of the pair inverts its half (the odd
+// half then multiplied by conj W_N1^n), the pair swaps halves with a lane shuffle and forms
+// Y[n] = A[n] + B[n] or Y[n + N2] = A[n] - B[n]. Stage-1 outputs are stored at
+// N1 k2 + (n1 XOR k2) against LDS bank conflicts, as in LineTile.
+template <int N, int NL, int T>
+struct LineTileW {
+  static constexpr int N2 = N == 512 ? 16 : (N == 128 ? 8 : 4);
+  static constexpr int N1 = 2 * N2;
+  static_assert(N1 * N2 == N, "N must be 2 N2^2");
+  static_assert(T % N1 == 0 && NL == T / N1, "a block is one round of T / N1 lines");
+  static_assert(WAVE % N1 == 0, "the threads of a line must share a wavefront");
+  __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ k2); }
+
+  // In-place transform of all NL lines. Caller syncs before (data in LDS) and after.
+  template <bool INV>
+  __device__ __forceinline__ static void run(float2* lds, int LS, int ES, const float2* __restrict__ tw) {
+    const int t = opaque_tid();
+    const int q = t % N1, lr = t / N1;
+    const int k2 = q >> 1, h = q & 1;
+    float2* base = lds + lr * LS;
+    if constexpr (!INV) {
+      float2 u[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[(q + N1 * n2) * ES];
+      Dft<N2, false>::run(u);
+#pragma unroll
+      for (int j = 1; j < N2; ++j) u[j] = cmul(u[j], tw[q * j]);
+#pragma unroll
+      for (int j = 0; j < N2; ++j) base[sw(q, j) * ES] = u[j];
+      __syncthreads();
+      float2 v[N2];
+#pragma unroll
+      for (int n = 0; n < N2; ++n) {
+        const float2 a = base[sw(n, k2) * ES], b = base[sw(n + N2, k2) * ES];
+        v[n] = h == 0 ? cadd(a, b) : cmul(csub(a, b), tw[(N / N1) * n]);
+      }
+      Dft<N2, false>::run(v);
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < N2; ++m) base[(k2 + N2 * (2 * m + h)) * ES] = v[m];
+    } else {
+      float2 v[N2];
+#pragma unroll
+      for (int m = 0; m < N2; ++m) v[m] = base[(k2 + N2 * (2 * m + h)) * ES];
+      Dft<N2, true>::run(v);
+      if (h) {
+#pragma unroll
+        for (int n = 0; n < N2; ++n) v[n] = cmul_conjb(v[n], tw[(N / N1) * n]);
+      }
+#pragma unroll
+      for (int n = 0; n < N2; ++n) {
+        float2 o;
+        o.x = __shfl_xor(v[n].x, 1);
+        o.y = __shfl_xor(v[n].y, 1);
+        v[n] = h == 0 ? cadd(v[n], o) : csub(o, v[n]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int n = 0; n < N2; ++n) base[sw(n + N2 * h, k2) * ES] = v[n];
+      __syncthreads();
+      float2 u[N2];
+#pragma unroll
+      for (int j = 0; j < N2; ++j) u[j] = base[sw(q, j) * ES];
+#pragma unroll
+      for (int j = 1; j < N2; ++j) u[j] = cmul_conjb(u[j], tw[q * j]);
+      Dft<N2, true>::run(u);
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) base[(q + N1 * n2) * ES] = u[n2];
+    }
+  }
+};
+
 }  // namespace ptyhip

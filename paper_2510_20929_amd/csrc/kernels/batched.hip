@@ -6,7 +6,7 @@
 // to their work (positions x modes x transform cost); every workgroup reads its
 // dataset's call arguments from a device descriptor table (sorted by class, then by
 // first workgroup) and runs the same per-position body as the per-plan kernels (512
-// threads for the on-chip frames and 512^2, 1024 for 256^2). Gather, probe reduction
+// threads for the on-chip frames, 1024 for 256^2 and 512^2). Gather, probe reduction
 // and final reductions follow per dataset; they too read their pointers from the
 // table, so a captured graph stays valid when the caller rebinds buffers.
 #include "big_body.hpp"
@@ -108,7 +108,7 @@ hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab,
     switch (c) {
       case 0: hipLaunchKernelGGL(batched_small_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
       case 1: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
-      default: hipLaunchKernelGGL((batched_big_kernel<512, 512>), grid, dim3(512), 0, st, t, cls_count[c]); break;
+      default: hipLaunchKernelGGL((batched_big_kernel<512, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
     }
   }
   for (int d = 0; d < n; ++d) {

@@ -27,12 +27,25 @@ namespace ptyhip {
 
 constexpr int BIG_MAX_EIG = 16;
 
+// Line transform of a block: one round of T / N1 lines. 512-point lines with 1024
+// threads use the wide form (32 lanes per line), which keeps the block at 32 lines.
+template <int N, int TT>
+struct BigLine {
+  using type = LineTile<N, TT / Split<N>::N1, TT>;
+  static constexpr int RB = TT / Split<N>::N1;
+};
+template <>
+struct BigLine<512, 1024> {
+  using type = LineTileW<512, 32, 1024>;
+  static constexpr int RB = 32;
+};
+
 template <int N, int TT>
 struct Big {
   static constexpr int T = TT;
-  // lines per block (row and column passes): one round of the line transform, T / N1
-  // lines (N1 lanes per line)
-  static constexpr int RB = TT / Split<N>::N1;
+  using LT = typename BigLine<N, TT>::type;
+  // lines per block (row and column passes)
+  static constexpr int RB = BigLine<N, TT>::RB;
   static_assert(N % RB == 0, "the blocks must tile the frame");
   static constexpr int RP = N + 1;                // row-tile pitch
   static constexpr int CP = RB + 1;               // column-tile pitch
@@ -69,15 +82,15 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   using B = Big<N, TT>;
   constexpr int T = B::T, NN = B::NN, RB = B::RB, RP = B::RP, CP = B::CP, WN = B::WN, NB = B::NB;
   constexpr int NW = T / WAVE;
-  constexpr int N1 = Split<N>::N1;
+  constexpr int CJ = T / RB;  // rows of a column block per element step
   // Every element loop over a line block has the same fixed trip count per thread (PER),
   // so it is unrolled and its global loads are issued together; loops whose elements
   // need several loads (eigenprobes, patch taps) go in batches of BAT pixels.
   constexpr int PER = RB * N / T;
   constexpr int BAT = PER < 8 ? PER : 8;
-  static_assert(PER * T == RB * N && PER % BAT == 0 && RB * N1 == T, "line blocks must split evenly");
+  static_assert(PER * T == RB * N && PER % BAT == 0 && RB * CJ == T, "line blocks must split evenly");
   // Element j of a thread: in a row block, frame pixel rb RB N + tid + j T (row RR(j) +
-  // tid / N, column tid % N when T >= N); in a column block, pixel (tid / RB + j N1) N +
+  // tid / N, column tid % N when T >= N); in a column block, pixel (tid / RB + j CJ) N +
   // cb RB + tid % RB. The thread part is a vector offset, the rest a scalar offset, so
   // the unrolled loads need no per-element address registers.
   constexpr int RRJ = T >= N ? T / N : 0;
@@ -127,11 +140,11 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   };
   const auto cols_to_frame = [&](int cb) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) fr.st(t_col[j * N1 * CP], v_col, (cb * RB + j * N1 * N) * 8);
+    for (int j = 0; j < PER; ++j) fr.st(t_col[j * CJ * CP], v_col, (cb * RB + j * CJ * N) * 8);
   };
   const auto frame_to_cols = [&](int cb) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) t_col[j * N1 * CP] = fr.ld(v_col, (cb * RB + j * N1 * N) * 8);
+    for (int j = 0; j < PER; ++j) t_col[j * CJ * CP] = fr.ld(v_col, (cb * RB + j * CJ * N) * 8);
   };
 
   for (int k = wg; k < a.K; k += nwg) {
@@ -216,7 +229,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
           }
           __syncthreads();
-          LineTile<N, RB, T>::template run<false>(tile, RP, 1, tws);
+          B::LT::template run<false>(tile, RP, 1, tws);
           __syncthreads();
           rows_to_frame(rb);
           __syncthreads();
@@ -226,18 +239,18 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         for (int cb = 0; cb < NB; ++cb) {
           frame_to_cols(cb);
           __syncthreads();
-          LineTile<N, RB, T>::template run<false>(tile, 1, CP, tws);
+          B::LT::template run<false>(tile, 1, CP, tws);
           __syncthreads();
           if (a.mode == MODE_APPLY_A) {
 #pragma unroll
             for (int j = 0; j < PER; ++j)
-              a.psi_out[(size_t(k) * M + m) * NN + pix_col0 + cb * RB + j * N1 * N] = cscale(t_col[j * N1 * CP], inv_n);
+              a.psi_out[(size_t(k) * M + m) * NN + pix_col0 + cb * RB + j * CJ * N] = cscale(t_col[j * CJ * CP], inv_n);
           } else if (!last) {
             const BufFrame pb(Ps + size_t(m) * NN, NN * 8);
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
-              const int so = cb * RB + j * N1 * N;
-              const float2 v = cscale(t_col[j * N1 * CP], inv_n);
+              const int so = cb * RB + j * CJ * N;
+              const float2 v = cscale(t_col[j * CJ * CP], inv_n);
               if (fa) pb.st(v, v_col, so * 8);
               cfb.stf((m == 0 ? 0.f : cfb.ldf(v_col / 2, so * 4)) + cabs2(v), v_col / 2, so * 4);
             }
@@ -248,14 +261,14 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
               int ci[BAT];
 #pragma unroll
               for (int j = 0; j < BAT; ++j) {
-                const int ky = tid / RB + (b0 + j) * N1, kx = cb * RB + tid % RB;
+                const int ky = tid / RB + (b0 + j) * CJ, kx = cb * RB + tid % RB;
                 ci[j] = centred_index(ky, kx, N);
                 imv[j] = imb.ldf(ci[j] * 4, 0);
-                cfv[j] = m == 0 ? 0.f : cfb.ldf(v_col / 2, (cb * RB + (b0 + j) * N1 * N) * 4);
+                cfv[j] = m == 0 ? 0.f : cfb.ldf(v_col / 2, (cb * RB + (b0 + j) * CJ * N) * 4);
               }
 #pragma unroll
               for (int j = 0; j < BAT; ++j) {
-                float2& tv = t_col[(b0 + j) * N1 * CP];
+                float2& tv = t_col[(b0 + j) * CJ * CP];
                 const float2 v = cscale(tv, inv_n);
                 const float I = cfv[j] + cabs2(v);
                 float l, c;
@@ -263,7 +276,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
                 if (a.ipred) a.ipred[size_t(k) * NN + ci[j]] = I;
                 lsum += double(l);
                 if (fa) {
-                  if (M > 1) cfb.stf(c, v_col / 2, (cb * RB + (b0 + j) * N1 * N) * 4);
+                  if (M > 1) cfb.stf(c, v_col / 2, (cb * RB + (b0 + j) * CJ * N) * 4);
                   tv = cscale(v, a.gscale * c);
                 }
               }
@@ -271,7 +284,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           }
           if (fa && last) {
             __syncthreads();
-            LineTile<N, RB, T>::template run<true>(tile, 1, CP, tws);
+            B::LT::template run<true>(tile, 1, CP, tws);
             __syncthreads();
             cols_to_frame(cb);
           }
@@ -317,12 +330,12 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         for (int cb = 0; cb < NB; ++cb) {
 #pragma unroll
           for (int j = 0; j < PER; ++j) {
-            const int so = cb * RB + j * N1 * N;
+            const int so = cb * RB + j * CJ * N;
             const float2 v = src.ld(v_col, so * 8);
-            t_col[j * N1 * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
+            t_col[j * CJ * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
           }
           __syncthreads();
-          LineTile<N, RB, T>::template run<true>(tile, 1, CP, tws);
+          B::LT::template run<true>(tile, 1, CP, tws);
           __syncthreads();
           cols_to_frame(cb);
           __syncthreads();
@@ -333,7 +346,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       for (int rb = 0; rb < NB; ++rb) {
         frame_to_rows(rb);
         __syncthreads();
-        LineTile<N, RB, T>::template run<true>(tile, RP, 1, tws);
+        B::LT::template run<true>(tile, RP, 1, tws);
         __syncthreads();
         for (int b0 = 0; b0 < PER; b0 += BAT) {
           float2 g[BAT], gP[BAT], P[BAT];

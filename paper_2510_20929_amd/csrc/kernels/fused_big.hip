@@ -1,16 +1,16 @@
 // Fused forward + adjoint kernels for 256^2 and 512^2 frames (thin wrappers over
 // big_body) and the probe-gradient reduction. Two layouts: variant 0 runs one
-// workgroup per CU (1024 threads for 256^2, 512 for 512^2) whose line blocks fill most
-// of the LDS; variant 1 runs two workgroups per CU with half the threads and half the
-// block, so that one workgroup's loads and stores overlap the other's transforms.
+// workgroup of 1024 threads per CU whose line blocks fill most of the LDS (512-point
+// lines use the wide line transform, 32 lanes per line); variant 1 runs two workgroups
+// per CU with fewer threads and smaller blocks (512 threads for 256^2, 256 for 512^2).
 #include "big_body.hpp"
 #include "launch.hpp"
 
 namespace ptyhip {
 
 int fused_big_threads(int N, int variant) {
-  const int t = N == 256 ? 1024 : 512;
-  return variant == 1 ? t / 2 : t;
+  if (variant != 1) return 1024;
+  return N == 256 ? 512 : 256;
 }
 
 int fused_big_wg_per_cu(int variant) { return variant == 1 ? 2 : 1; }
@@ -131,7 +131,7 @@ hipError_t launch_fused_big(const CallArgs& a, int N, int variant, int grid, hip
   const bool two = variant == 1;
   switch (N) {
     case 256: return two ? launch_big_t<256, 512>(a, grid, st) : launch_big_t<256, 1024>(a, grid, st);
-    case 512: return two ? launch_big_t<512, 256>(a, grid, st) : launch_big_t<512, 512>(a, grid, st);
+    case 512: return two ? launch_big_t<512, 256>(a, grid, st) : launch_big_t<512, 1024>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
