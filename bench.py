@@ -79,6 +79,25 @@ def read_traffic(khash: str, kernel: str):
     return t.get("bytes_per_launch")
 
 
+def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM bandwidth on this GPU: a device-to-device copy of `nbytes`, timed with
+    events on the current stream (median of `reps`); read + written bytes per second, GB/s."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del x, y
+    times.sort()
+    return 2.0 * nbytes / (times[len(times) // 2] * 1e-3) / 1e9
+
+
 def cpu_baseline(truth, start, budget_s: float = 10.0, pool_s: float = 8.0):
     """The FP64 oracle (as it stands) on the same workload on the host: forward + adjoint
     over the positions in chunks of 25, cycling through all positions until the time
@@ -333,6 +352,7 @@ def main():
     khash = kernel_hash()
     headline = args.workload == "c1"
     traffic = read_traffic(khash, kernel_name(plan, start, tune)) if headline else None
+    copy_gbs = copy_bandwidth(torch, dev)  # achievable HBM bandwidth, outside the timed region
 
     plain = None
     if not args.no_plain:
@@ -368,7 +388,9 @@ def main():
                      "traffic": traffic, "kernel": kernel_name(plan, start, tune),
                      "kernel_ms": k_avg_ms, "launches_per_step": launches, "kernel_ms_per_step": k_step_ms,
                      "flops_per_pattern": flops_pp},
-        "hbm": {"alg_bytes_per_pattern": bytes_pp, "alg_GBs": hbm_alg_gbs, "frac_of_peak": hbm_alg_gbs / HBM_PEAK_GBS},
+        "hbm": {"alg_bytes_per_pattern": bytes_pp, "alg_GBs": hbm_alg_gbs, "frac_of_peak": hbm_alg_gbs / HBM_PEAK_GBS,
+                "copy_GBs": copy_gbs, "frac_of_copy": hbm_alg_gbs / copy_gbs,
+                "counter_GBs": (traffic / (k_avg_ms * 1e-3) / 1e9) if traffic else None},
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
         "cpu_baseline": cpu,
