@@ -312,8 +312,15 @@ struct LineTile {
   // which in natural order would all hit one bank.
   __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ (k2 & (N1 - 1))); }
 
+  // twiddle W_N^{n1 k2}: natural table tw[n1 k2], or (TWT) the transposed table with
+  // entry (k2, n1) at k2 N1 + n1, whose reads by the N1 lanes of a line are contiguous
+  template <bool TWT>
+  __device__ __forceinline__ static float2 twid(const float2* __restrict__ tw, int n1, int k2) {
+    return TWT ? tw[k2 * N1 + n1] : tw[n1 * k2];
+  }
+
   // In-place transform of all NL lines. Caller syncs before (data in LDS) and after.
-  template <bool INV>
+  template <bool INV, bool TWT = false>
   __device__ __forceinline__ static void run(float2* lds, int LS, int ES, const float2* __restrict__ tw_) {
     const int t = opaque_tid();
     const float2* __restrict__ tw = tw_;
@@ -328,7 +335,7 @@ struct LineTile {
         for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[(q + N1 * n2) * ES];
         Dft<N2, false>::run(u);
 #pragma unroll
-        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul(u[k2], tw[q * k2]);
+        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul(u[k2], twid<TWT>(tw, q, k2));
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) base[sw(q, k2) * ES] = u[k2];
       }
@@ -387,7 +394,7 @@ struct LineTile {
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) u[k2] = base[sw(q, k2) * ES];
 #pragma unroll
-        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul_conjb(u[k2], tw[q * k2]);
+        for (int k2 = 1; k2 < N2; ++k2) u[k2] = cmul_conjb(u[k2], twid<TWT>(tw, q, k2));
         Dft<N2, true>::run(u);
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) base[(q + N1 * n2) * ES] = u[n2];
@@ -418,8 +425,11 @@ struct LineTileW {
   __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ k2); }
 
   // In-place transform of all NL lines. Caller syncs before (data in LDS) and after.
-  template <bool INV>
+  // `tw` is the transposed twiddle table: W_N^{n1 k2} at k2 N1 + n1 (N entries); the
+  // stage-2 twiddle W_N1^n = W_N^{(N / N1) n} is its entry (k2 = n, n1 = N / N1).
+  template <bool INV, bool TWT = true>
   __device__ __forceinline__ static void run(float2* lds, int LS, int ES, const float2* __restrict__ tw) {
+    static_assert(TWT, "the wide line transform reads the transposed twiddle table");
     const int t = opaque_tid();
     const int q = t % N1, lr = t / N1;
     const int k2 = q >> 1, h = q & 1;
@@ -430,7 +440,7 @@ struct LineTileW {
       for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[(q + N1 * n2) * ES];
       Dft<N2, false>::run(u);
 #pragma unroll
-      for (int j = 1; j < N2; ++j) u[j] = cmul(u[j], tw[q * j]);
+      for (int j = 1; j < N2; ++j) u[j] = cmul(u[j], tw[j * N1 + q]);
 #pragma unroll
       for (int j = 0; j < N2; ++j) base[sw(q, j) * ES] = u[j];
       __syncthreads();
@@ -438,7 +448,7 @@ struct LineTileW {
 #pragma unroll
       for (int n = 0; n < N2; ++n) {
         const float2 a = base[sw(n, k2) * ES], b = base[sw(n + N2, k2) * ES];
-        v[n] = h == 0 ? cadd(a, b) : cmul(csub(a, b), tw[(N / N1) * n]);
+        v[n] = h == 0 ? cadd(a, b) : cmul(csub(a, b), tw[n * N1 + N / N1]);
       }
       Dft<N2, false>::run(v);
       __syncthreads();
@@ -451,7 +461,7 @@ struct LineTileW {
       Dft<N2, true>::run(v);
       if (h) {
 #pragma unroll
-        for (int n = 0; n < N2; ++n) v[n] = cmul_conjb(v[n], tw[(N / N1) * n]);
+        for (int n = 0; n < N2; ++n) v[n] = cmul_conjb(v[n], tw[n * N1 + N / N1]);
       }
 #pragma unroll
       for (int n = 0; n < N2; ++n) {
@@ -468,7 +478,7 @@ struct LineTileW {
 #pragma unroll
       for (int j = 0; j < N2; ++j) u[j] = base[sw(q, j) * ES];
 #pragma unroll
-      for (int j = 1; j < N2; ++j) u[j] = cmul_conjb(u[j], tw[q * j]);
+      for (int j = 1; j < N2; ++j) u[j] = cmul_conjb(u[j], tw[j * N1 + q]);
       Dft<N2, true>::run(u);
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) base[(q + N1 * n2) * ES] = u[n2];

@@ -60,7 +60,7 @@ template <int N, int TT>
 struct BigShared {
   float2 tile[Big<N, TT>::LDS];
   float2 prevg[2][N];  // last patch-gradient row of the previous row block (double-buffered)
-  float2 tw[N];        // twiddle table W_N^i of the line transforms
+  float2 tw[N];        // twiddles of the line transforms, transposed: W_N^{n1 k2} at k2 N1 + n1
   double red[2 * (TT / WAVE)];
   double wred[BIG_MAX_EIG * (TT / WAVE)];
   float wsh[BIG_MAX_EIG];
@@ -126,7 +126,10 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   if ((a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH) && a.zero_acc && want_probe && !a.gpstage)
     for (size_t i = tid; i < size_t(a.E) * M * NN; i += T) pacc[i] = make_float2(0.f, 0.f);
   float2* tws = sh.tw;
-  for (int i = tid; i < N; i += T) tws[i] = a.tw[i];
+  {
+    using LT = typename B::LT;
+    for (int i = tid; i < N; i += T) tws[i] = a.tw[(i % LT::N1) * (i / LT::N1)];
+  }
   __syncthreads();
 
   // line-block copies between the work frame and the LDS tile
@@ -229,7 +232,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
           }
           __syncthreads();
-          B::LT::template run<false>(tile, RP, 1, tws);
+          B::LT::template run<false, true>(tile, RP, 1, tws);
           __syncthreads();
           rows_to_frame(rb);
           __syncthreads();
@@ -239,7 +242,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         for (int cb = 0; cb < NB; ++cb) {
           frame_to_cols(cb);
           __syncthreads();
-          B::LT::template run<false>(tile, 1, CP, tws);
+          B::LT::template run<false, true>(tile, 1, CP, tws);
           __syncthreads();
           if (a.mode == MODE_APPLY_A) {
 #pragma unroll
@@ -284,7 +287,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           }
           if (fa && last) {
             __syncthreads();
-            B::LT::template run<true>(tile, 1, CP, tws);
+            B::LT::template run<true, true>(tile, 1, CP, tws);
             __syncthreads();
             cols_to_frame(cb);
           }
@@ -335,7 +338,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             t_col[j * CJ * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
           }
           __syncthreads();
-          B::LT::template run<true>(tile, 1, CP, tws);
+          B::LT::template run<true, true>(tile, 1, CP, tws);
           __syncthreads();
           cols_to_frame(cb);
           __syncthreads();
@@ -346,7 +349,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       for (int rb = 0; rb < NB; ++rb) {
         frame_to_rows(rb);
         __syncthreads();
-        B::LT::template run<true>(tile, RP, 1, tws);
+        B::LT::template run<true, true>(tile, RP, 1, tws);
         __syncthreads();
         for (int b0 = 0; b0 < PER; b0 += BAT) {
           float2 g[BAT], gP[BAT], P[BAT];
