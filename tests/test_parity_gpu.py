@@ -138,6 +138,22 @@ def test_fourstep_layouts(N, E, variant):
     assert got["flags"] == 0
 
 
+@pytest.mark.parametrize("N,E", [(256, 3), (512, 1)])
+def test_fourstep_bitwise_reproducible(N, E):
+    """Two identical fused calls give bitwise-identical loss and gradients: the four-step
+    kernel, the staged eigenprobe reduction, the window gather and the FP64 partial sums
+    all add in a fixed order (no atomics)."""
+    start, I = custom_problem(950 + N + E, N, 2, E, 1, N * 2 + 60, 24, loss="poisson",
+                              weights="opr" if E > 1 else "amp")
+    grads = ("obj", "probe", "pos", "weights")
+    plan = _plan(start)
+    a = run_gpu(plan, start, I, grads)
+    b = run_gpu(plan, start, I, grads)
+    assert a["flags"] == 0 and b["flags"] == 0
+    for key in ("loss", "I_pred", "g_obj", "g_probe", "g_pos", "g_weights"):
+        assert np.array_equal(np.asarray(a[key]), np.asarray(b[key])), key
+
+
 @pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
 def test_config5_mode_heavy(plain):
     """Config 5 structure (30 probe modes of 128^2, 413 x 535 object, raster with sub-pixel
