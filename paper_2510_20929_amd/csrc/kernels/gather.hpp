@@ -1,6 +1,6 @@
 // Object gradient from the per-position window gradients: the transpose of the patch
 // extraction summed over positions, done as a gather. Each workgroup owns a 32 x 32
-// tile of one slice and walks the positions in order (staged through LDS), adding the
+// (or, for objects too small to fill the GPU with such tiles, 16 x 16) tile of one slice and walks the positions in order (staged through LDS), adding the
 // part of every valid window that covers the tile. Every object pixel is written
 // exactly once (no atomics, fixed summation order).
 #pragma once
@@ -19,14 +19,15 @@ template <class V> __device__ __forceinline__ V vzero();
 template <> __device__ __forceinline__ float vzero<float>() { return 0.f; }
 template <> __device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
 
-// One 32 x 32 tile (blockIdx.x, blockIdx.y) of slice blockIdx.z; 256 threads (4 waves).
+// One TS x TS tile (blockIdx.x, blockIdx.y) of slice blockIdx.z; 256 threads (4 waves),
+// each owning TS^2 / 256 pixels of a column.
 // Positions are taken in chunks: every thread tests a few positions for overlap with the
 // tile, the hits are compacted in position order (wave ballots + a block prefix, so the
 // order never depends on timing), and then each thread adds the window values of the
 // hits at its 4 pixels, issuing the loads of 4 hits before adding them in order.
 // `win` holds [K][S][N+1][N+1] windows of value type V (float2 gradients, float
 // illumination), `out` the [S][H][W] result.
-template <class V>
+template <class V, int TS = GT>
 __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const int* __restrict__ wvalid,
                                               const float* __restrict__ pos, V* out_all, int K, int S, int N,
                                               int H, int W, int accumulate) {
@@ -34,14 +35,17 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
   constexpr int NT = 256;
   __shared__ int hy[CH], hx[CH], hk[CH];
   __shared__ int wcnt[NT / 64];
+  constexpr int RPP = NT / TS;  // rows per pass
+  constexpr int PJ = TS / RPP;   // passes (pixels per thread)
+  static_assert(RPP * TS == NT && PJ * RPP == TS, "the tile must split evenly over the threads");
   const int WN = N + 1;
-  const int tx0 = blockIdx.x * GT, ty0 = blockIdx.y * GT, s = blockIdx.z;
-  const int c = threadIdx.x % GT, r0 = threadIdx.x / GT;  // 8 rows per pass, 4 passes
+  const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS, s = blockIdx.z;
+  const int c = threadIdx.x % TS, r0 = threadIdx.x / TS;
   const int x = tx0 + c;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  V acc[4];
+  V acc[PJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = vzero<V>();
+  for (int j = 0; j < PJ; ++j) acc[j] = vzero<V>();
   const size_t wsz = size_t(WN) * WN;
   const V z = vzero<V>();
   for (int k0 = 0; k0 < K; k0 += CH) {
@@ -56,7 +60,7 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
       if (i < n && wvalid[k]) {
         y0 = int(floorf(pos[2 * k]));
         x0 = int(floorf(pos[2 * k + 1]));
-        hit = !(y0 > ty0 + GT - 1 || y0 + WN - 1 < ty0 || x0 > tx0 + GT - 1 || x0 + WN - 1 < tx0);
+        hit = !(y0 > ty0 + TS - 1 || y0 + WN - 1 < ty0 || x0 > tx0 + TS - 1 || x0 + WN - 1 < tx0);
       }
       const unsigned long long b = __ballot(hit);
       if (lane == 0) wcnt[wid] = __popcll(b);
@@ -77,7 +81,7 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
       __syncthreads();  // wcnt is rewritten by the next round; the hits are visible
     }
     for (int h = 0; h < nh; h += 4) {
-      V t[4][4];
+      V t[4][PJ];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool on = h + u < nh;
@@ -85,22 +89,22 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
         const int y0 = hy[hh], px = on ? x - hx[hh] : -1;
         const V* w = win + (size_t(hk[hh]) * S + s) * wsz;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int py = ty0 + r0 + 8 * j - y0;
+        for (int j = 0; j < PJ; ++j) {
+          const int py = ty0 + r0 + RPP * j - y0;
           t[u][j] = (px >= 0 && px < WN && py >= 0 && py < WN) ? w[size_t(py) * WN + px] : z;
         }
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = vadd(acc[j], t[u][j]);
+        for (int j = 0; j < PJ; ++j) acc[j] = vadd(acc[j], t[u][j]);
     }
   }
   if (x >= W) return;
   V* out = out_all + size_t(s) * H * W;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int y = ty0 + r0 + 8 * j;
+  for (int j = 0; j < PJ; ++j) {
+    const int y = ty0 + r0 + RPP * j;
     if (y < H) {
       V* o = out + size_t(y) * W + x;
       *o = accumulate ? vadd(*o, acc[j]) : acc[j];
