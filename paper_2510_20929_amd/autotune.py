@@ -1,8 +1,9 @@
 """Autotuner for the fused forward + adjoint and the batched launch.
 
 For a problem shape it enumerates implementation choices (thread layout of the
-on-chip kernel, storing vs recomputing far fields / incident waves, persistent grid
-size; for batches the total workgroup count, or one call per dataset), runs every
+on-chip kernel or of the four-step kernel, storing vs recomputing far fields /
+incident waves, persistent grid size; for batches the workgroup count of each
+frame-size class's launch, or one call per dataset), runs every
 candidate once and keeps it only if its loss and gradients agree with the per-step
 form on the same inputs (forward <= 1e-5, gradients <= 1e-4 relative L2), then times
 the survivors with HIP events (median of several launches) and caches the fastest

@@ -138,11 +138,11 @@ def test_fourstep_layouts(N, E, variant):
     assert got["flags"] == 0
 
 
-@pytest.mark.parametrize("N,E", [(256, 3), (512, 1)])
-def test_fourstep_bitwise_reproducible(N, E):
-    """Two identical fused calls give bitwise-identical loss and gradients: the four-step
-    kernel, the staged eigenprobe reduction, the window gather and the FP64 partial sums
-    all add in a fixed order (no atomics)."""
+@pytest.mark.parametrize("N,E", [(128, 2), (256, 3), (512, 1)])
+def test_fused_bitwise_reproducible(N, E):
+    """Two identical fused calls give bitwise-identical loss and gradients: the on-chip
+    and four-step kernels, the per-workgroup and staged probe reductions, the window
+    gather and the FP64 partial sums all add in a fixed order (no atomics)."""
     start, I = custom_problem(950 + N + E, N, 2, E, 1, N * 2 + 60, 24, loss="poisson",
                               weights="opr" if E > 1 else "amp")
     grads = ("obj", "probe", "pos", "weights")
