@@ -246,7 +246,7 @@ ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);
 ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
 
 /* Many independent reconstructions of uneven frame sizes in one persistent launch per
- * frame-size class (64^2/128^2, 256^2, 512^2), captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
+ * frame size (64^2, 128^2, 256^2, 512^2), captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
  * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. */
 ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, int32_t n, const ptyhip_tune* tune,
                                   ptyhip_batch* out);

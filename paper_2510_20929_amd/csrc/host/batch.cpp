@@ -29,9 +29,9 @@ struct Bound {
 struct ptyhip_batch_s {
   int n = 0;
   int device = 0;
-  int cls_first[BATCH_CLASSES] = {0, 0, 0};  // table entries of each class (sorted table)
-  int cls_count[BATCH_CLASSES] = {0, 0, 0};
-  int cls_wg[BATCH_CLASSES] = {0, 0, 0};     // workgroups of each class's launch
+  int cls_first[BATCH_CLASSES] = {};  // table entries of each class (sorted table)
+  int cls_count[BATCH_CLASSES] = {};
+  int cls_wg[BATCH_CLASSES] = {};     // workgroups of each class's launch
   std::vector<Plan*> plans;
   std::vector<int> K, first_wg, n_wg;
   std::vector<Bound> bound;
@@ -138,8 +138,10 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     ptyhip_tune t{};
     if (tune) t = *tune;
     t.grid = std::max(b->n_wg[i], prop.multiProcessorCount);
-    t.variant = 0;
-    t.recompute = 0;
+    // the body each class's launch runs: 128^2 the register-resident patch layout with
+    // recomputed far fields (several modes), the others the default layout
+    t.variant = batch_variant(descs[i].frame);
+    t.recompute = (descs[i].frame == 128 && descs[i].n_modes > 1) ? 1 : 0;
     if (t.plain_chunk <= 0) t.plain_chunk = 128;
     p->whole_windows = true;
     ptyhip_status s = plan_init(p, descs[i], std::max(K[i], 1), &t);
@@ -147,10 +149,9 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
       delete b;
       return s;
     }
-    // the batched launch runs the on-chip bodies with 512 threads: size its scratch for that
-    // (the four-step bodies' scratch does not depend on the thread count)
+    // the batched launch runs the same bodies: its scratch layout must be the plan's
     size_t off = 0;
-    const size_t need = batched_scratch_elems(descs[i].frame, descs[i].n_modes, descs[i].n_eig, &off);
+    const size_t need = batched_scratch_elems(descs[i].frame, descs[i].n_modes, descs[i].n_eig, t.recompute, &off);
     if (need > p->scratch_stride || off != p->pacc_off) {
       delete b;
       return PTYHIP_EUNSUPPORTED;

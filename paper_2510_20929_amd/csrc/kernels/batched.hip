@@ -1,12 +1,12 @@
 // Many independent reconstructions of uneven frame size in a few persistent launches.
 //
-// Datasets are grouped by frame-size class (on-chip 64^2 / 128^2, four-step 256^2,
-// four-step 512^2) and each class runs as one persistent launch with that class's best
-// thread layout. A launch's workgroups are partitioned among its datasets in proportion
+// Datasets are grouped by frame size (64^2, 128^2, 256^2, 512^2) and each class runs as
+// one persistent launch with that class's thread layout. A launch's workgroups are partitioned among its datasets in proportion
 // to their work (positions x modes x transform cost); every workgroup reads its
 // dataset's call arguments from a device descriptor table (sorted by class, then by
 // first workgroup) and runs the same per-position body as the per-plan kernels (512
-// threads for the on-chip frames, 1024 for 256^2 and 512^2). Gather, probe reduction
+// threads for 64^2; 1024 for 128^2, with the patch in registers, and for the four-step
+// frames 256^2 and 512^2). Gather, probe reduction
 // and final reductions follow per dataset; they too read their pointers from the
 // table, so a captured graph stays valid when the caller rebinds buffers.
 #include "big_body.hpp"
@@ -18,10 +18,7 @@ namespace ptyhip {
 
 constexpr int BT = 512;
 
-union SmallBatchShared {
-  SmallShared<64, BT> s64;
-  SmallShared<128, BT> s128;
-};
+constexpr int BT128 = 1024;  // 128^2: the register-resident patch layout (tuning variant 4)
 
 // the dataset of this workgroup within the class's entries tab[0..n)
 __device__ __forceinline__ int batch_dataset(const BatchEntry* __restrict__ tab, int n) {
@@ -30,18 +27,22 @@ __device__ __forceinline__ int batch_dataset(const BatchEntry* __restrict__ tab,
   return d;
 }
 
-__global__ __launch_bounds__(BT) void batched_small_kernel(const BatchEntry* __restrict__ tab, int n) {
-  __shared__ SmallBatchShared sh;
+__global__ __launch_bounds__(BT) void batched_64_kernel(const BatchEntry* __restrict__ tab, int n) {
+  __shared__ SmallShared<64, BT> sh;
   const int d = batch_dataset(tab, n);
   const CallArgs a = tab[d].a;
   const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
-  switch (tab[d].N * 2 + a.loss) {
-    case 128: small_body<64, BT, 0>(a, sh.s64, wg, nwg); break;
-    case 129: small_body<64, BT, 1>(a, sh.s64, wg, nwg); break;
-    case 256: small_body<128, BT, 0>(a, sh.s128, wg, nwg); break;
-    case 257: small_body<128, BT, 1>(a, sh.s128, wg, nwg); break;
-    default: break;
-  }
+  if (a.loss == 0) small_body<64, BT, 0>(a, sh, wg, nwg);
+  else small_body<64, BT, 1>(a, sh, wg, nwg);
+}
+
+__global__ __launch_bounds__(BT128) void batched_128_kernel(const BatchEntry* __restrict__ tab, int n) {
+  __shared__ SmallShared<128, BT128> sh;
+  const int d = batch_dataset(tab, n);
+  const CallArgs a = tab[d].a;
+  const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
+  if (a.loss == 0) small_body<128, BT128, 0, true, false>(a, sh, wg, nwg);
+  else small_body<128, BT128, 1, true, false>(a, sh, wg, nwg);
 }
 
 template <int N, int T>
@@ -54,10 +55,12 @@ __global__ __launch_bounds__(T) void batched_big_kernel(const BatchEntry* __rest
   else big_body<N, T, 1>(a, sh, wg, nwg);
 }
 
-int batch_class(int N) { return N <= 128 ? 0 : (N == 256 ? 1 : 2); }
+int batch_class(int N) { return N <= 64 ? 0 : (N == 128 ? 1 : (N == 256 ? 2 : 3)); }
 
-size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off) {
-  if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, 0, pacc_off, 0);
+int batch_variant(int N) { return N == 128 ? 4 : 0; }
+
+size_t batched_scratch_elems(int N, int M, int E, int recompute, size_t* pacc_off) {
+  if (N <= 128) return fused_small_scratch_elems(N, 1, M, E, recompute, pacc_off, batch_variant(N));
   return big_scratch_elems(N, M, E, pacc_off);
 }
 
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(256) void batch_gather_kernel(const BatchEntry* __r
 
 // probe gradient of dataset d: sum of its workgroups' accumulators; the on-chip bodies
 // store element i of thread t at i*T + t, the four-step bodies in natural order
-template <int N>
+template <int N, int T = BT>
 __global__ void batch_probe_reduce_kernel(const BatchEntry* __restrict__ tab, int d) {
   const CallArgs& a = tab[d].a;
   float2* out = tab[d].g_probe;
@@ -80,7 +83,7 @@ __global__ void batch_probe_reduce_kernel(const BatchEntry* __restrict__ tab, in
     float2 s = make_float2(0.f, 0.f);
     for (int w = 0; w < groups; ++w) s = cadd(s, src[size_t(w) * a.scratch_stride]);
     size_t pix = r;
-    if constexpr (N <= 128) pix = size_t(SmallCtx<N, BT>::a_pix(int(r % BT), int(r / BT)));
+    if constexpr (N <= 128) pix = size_t(SmallCtx<N, T>::a_pix(int(r % T), int(r / T)));
     out[em * NN + pix] = s;
   }
 }
@@ -106,8 +109,9 @@ hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab,
     const BatchEntry* t = dev_tab + cls_first[c];
     const dim3 grid{unsigned(cls_wg[c])};
     switch (c) {
-      case 0: hipLaunchKernelGGL(batched_small_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
-      case 1: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
+      case 0: hipLaunchKernelGGL(batched_64_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
+      case 1: hipLaunchKernelGGL(batched_128_kernel, grid, dim3(BT128), 0, st, t, cls_count[c]); break;
+      case 2: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
       default: hipLaunchKernelGGL((batched_big_kernel<512, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
     }
   }
@@ -124,7 +128,7 @@ hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab,
       if (blocks > 4096) blocks = 4096;
       switch (e.N) {
         case 64: hipLaunchKernelGGL(batch_probe_reduce_kernel<64>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
-        case 128: hipLaunchKernelGGL(batch_probe_reduce_kernel<128>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
+        case 128: hipLaunchKernelGGL((batch_probe_reduce_kernel<128, BT128>), dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
         case 256: hipLaunchKernelGGL(batch_probe_reduce_kernel<256>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
         case 512: hipLaunchKernelGGL(batch_probe_reduce_kernel<512>, dim3(unsigned(blocks)), dim3(256), 0, st, dev_tab, d); break;
         default: return hipErrorInvalidValue;

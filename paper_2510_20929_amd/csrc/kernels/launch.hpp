@@ -108,10 +108,12 @@ struct BatchEntry {
   int pad;
 };
 
-size_t batched_scratch_elems(int N, int M, int E, size_t* pacc_off);
-// frame-size classes of the batched launch: 0 = on chip (64^2, 128^2), 1 = 256^2, 2 = 512^2
-constexpr int BATCH_CLASSES = 3;
+size_t batched_scratch_elems(int N, int M, int E, int recompute, size_t* pacc_off);
+// frame-size classes of the batched launch: 64^2, 128^2, 256^2, 512^2, and the tuning
+// variant whose body (and scratch layout) each class runs
+constexpr int BATCH_CLASSES = 4;
 int batch_class(int N);
+int batch_variant(int N);
 hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
                           const int* cls_count, const int* cls_wg, hipStream_t st);
 
