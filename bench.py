@@ -129,6 +129,10 @@ def cpu_baseline(truth, start, budget_s: float = 10.0, pool_s: float = 8.0):
     one = {"value": done / dt, "cores": 1,
            "sample": f"{done} patterns ({done / n:.2f} passes over the {n} positions, chunks of 25), {dt:.1f} s"}
     workers = timing.host_workers()
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
     rate, pdone, wall = timing.pool_rate(start.obj, start.probe, start.positions, I_meas, workers=workers,
                                          budget_s=pool_s, chunk=chunk, **kw)
     print(f"# cpu baseline: {one['value']:.1f} patterns/s on one thread, {rate:.1f} on {workers} processes",
@@ -137,7 +141,10 @@ def cpu_baseline(truth, start, budget_s: float = 10.0, pool_s: float = 8.0):
             "sample": f"{pdone} patterns of the same workload ({n} positions split into {workers} shards, one "
                       f"single-threaded process each, chunks of 25), FP64 NumPy oracle, {wall:.1f} s wall",
             "single_thread": one,
-            "host_cpu": _host_cpu()}
+            "host_cpu": _host_cpu(),
+            "affinity_cpus": affinity,
+            "pool_cap": f"one worker per CPU this process may run on, at most {timing.HOST_SHARE} (the host CPUs "
+                        f"allotted to one GPU on the measuring machine)"}
 
 
 def _host_cpu() -> str:
@@ -263,6 +270,7 @@ def main():
                     help="synthetic workload (default: config 1, the headline measurement)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-step form")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd form")
     ap.add_argument("--tune", default=None,
                     help="fixed implementation choice as JSON (skips the autotuner; used for profiling runs)")
     ap.add_argument("--retune", action="store_true", help="ignore the frozen tune cache and autotune again")
@@ -372,6 +380,33 @@ def main():
                  "kernel_chain_ms": p_ms / max(p_n, 1),
                  "hbm_alg_frac": bytes_pp * K / (p_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
+    # the autograd form (torch.autograd.Function over the same plan): forward + backward
+    # of the loss with respect to the same leaves, timed the same way as the per-call form
+    autograd = None
+    if not args.no_autograd:
+        from paper_2510_20929_amd import ptycho_loss
+        leaves = {"obj": obj.clone().requires_grad_("obj" in grads),
+                  "probe": probe.clone().requires_grad_("probe" in grads),
+                  "pos": pos.clone().requires_grad_("pos" in grads)}
+        w_leaf = None if wts is None else wts.clone().requires_grad_("weights" in grads)
+
+        def ag_step():
+            for v in list(leaves.values()) + ([w_leaf] if w_leaf is not None else []):
+                v.grad = None
+            L = ptycho_loss(leaves["obj"], leaves["probe"], leaves["pos"], I_meas, plan, weights=w_leaf)
+            L.backward()
+
+        for _ in range(max(1, args.warmup)):
+            ag_step()
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        for _ in range(args.steps):
+            ag_step()
+        torch.cuda.synchronize()
+        a_ms = (time.perf_counter() - ta0) * 1e3 / args.steps
+        autograd = {"value": K / (a_ms * 1e-3), "ms_per_step": a_ms, "vs_per_call": ms_step / a_ms,
+                    "form": "PtychoLoss (torch.autograd.Function) forward + backward, same plan"}
+
     cpu = None
     if headline and not args.no_cpu:
         cpu = cpu_baseline(truth, start)
@@ -393,6 +428,7 @@ def main():
                 "counter_GBs": (traffic / (k_avg_ms * 1e-3) / 1e9) if traffic else None},
         "plain": plain,
         "fused_vs_plain": (value / plain["value"]) if plain else None,
+        "autograd": autograd,
         "cpu_baseline": cpu,
         "tune": tune,
         "tune_source": tune_src,

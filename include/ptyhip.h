@@ -152,8 +152,15 @@ const char* ptyhip_version(void);
 /* Pure host check of a description; no GPU needed. */
 ptyhip_status ptyhip_desc_validate(const ptyhip_desc* desc);
 
-/* Create a plan for up to max_positions positions per call on the current device.
- * tune may be NULL. Allocates the workspace; *out is NULL on failure. */
+/* Create a plan: one problem shape of the image-formation map I = F(o, p, Lambda) of
+ * Eq. (4) (frame size, incoherent modes, OPR eigenprobes and slices as in Sec. 2.1,
+ * Software design / Overview), for up to max_positions scan positions per call, on the
+ * current device. tune may be NULL (defaults). The plan allocates its whole workspace
+ * here (twiddle and propagator tables, per-position partial sums, per-workgroup scratch,
+ * window-gradient buffer, per-step buffers); it owns that memory until
+ * ptyhip_plan_destroy. Errors: EINVAL for a NULL out or a bad tune value, the
+ * ptyhip_desc_validate statuses, EBOUNDS for max_positions < 0, EHIP / ENOMEM when a
+ * device query or allocation fails. *out is NULL on any failure. */
 ptyhip_status ptyhip_plan_create(const ptyhip_desc* desc, int32_t max_positions, ptyhip_plan* out);
 ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positions, const ptyhip_tune* tune,
                                     ptyhip_plan* out);
@@ -188,7 +195,10 @@ ptyhip_status ptyhip_forward_adjoint_ex(ptyhip_plan plan, void* stream, int32_t 
                                         const float* I_meas, double* loss, float* I_pred, float* g_obj,
                                         float* g_probe, float* g_pos, float* g_weights, double* g_lambda_z);
 
-/* The linear map (object, probe) -> far-field waves Psi [K][M][N][N] (unshifted),
+/* The linear map (object, probe) -> far-field waves Psi [K][M][N][N] (unshifted):
+ * Eq. (4) before the modulus, i.e. the exit waves of Sec. 2.1 (patch extraction, probe
+ * times patch, multislice propagation) carried to the far field by the unitary DFT,
+ * with the object linear for a fixed probe and the probe linear for a fixed object;
  * and its adjoint (for the identity <A x, y> = <x, A^H y>): apply_AH takes Y [K][M][N][N]
  * and returns, per slice, the adjoint of O_s -> Psi (other slices and probe fixed) in
  * g_obj and the adjoint of U -> Psi (object fixed) in g_probe (either may be NULL). */
@@ -240,7 +250,12 @@ ptyhip_status ptyhip_orthogonalize_modes(ptyhip_plan plan, void* stream, const f
 ptyhip_status ptyhip_plan_set_timing(ptyhip_plan plan, int32_t enable);
 ptyhip_status ptyhip_plan_kernel_time(ptyhip_plan plan, double* total_ms, int32_t* launches);
 
-/* Synchronise `stream` and read the plan's device error latch (PTYHIP_FLAG_*). */
+/* Synchronise `stream` and read the plan's device error latch (PTYHIP_FLAG_*) into the
+ * host word *flags. The latch collects, over every call since the last clear, the
+ * positions the device had to drop: a patch window that leaves the object (the paper's
+ * patch extraction, Sec. 2.1, is silent on borders; this library neither wraps nor
+ * clamps) or a non-finite position or loss. Returns EINVAL for NULL arguments and EHIP
+ * if the synchronisation or the copy fails. */
 ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);
 /* Clear the latch (asynchronously on `stream`). */
 ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);

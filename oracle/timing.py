@@ -72,8 +72,13 @@ def pool_rate(obj, probe, positions, I_meas, *, workers: int, budget_s: float = 
     return done / wall, done, wall
 
 
-def host_workers(cap: int = 16) -> int:
-    """Worker count for the host: the CPUs this process may run on, at most ``cap``."""
+HOST_SHARE = 16  # host CPUs allotted to one GPU on the measuring machine
+
+
+def host_workers(cap: int = HOST_SHARE) -> int:
+    """Worker count for the host: the CPUs this process may run on, at most ``cap`` (the
+    measuring machine gives each GPU a share of 16 host CPUs, whatever the affinity mask
+    or the CPU count of the whole host shows, and caps a job's processes accordingly)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

@@ -7,10 +7,12 @@ frame-size class's launch, or one call per dataset), runs every
 candidate once and keeps it only if its loss and gradients agree with the per-step
 form on the same inputs (forward <= 1e-5, gradients <= 1e-4 relative L2), then times
 the survivors with HIP events (median of several launches) and caches the fastest
-in a JSON file keyed by GPU architecture and problem shape.
+in a JSON file keyed by GPU architecture, a hash of the library sources and the
+problem shape: an entry timed on other kernel sources is never used.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
@@ -25,6 +27,27 @@ FWD_TOL = 1e-5
 GRAD_TOL = 1e-4
 
 
+_SRC_HASH: Optional[str] = None
+
+
+def source_hash() -> str:
+    """Hash of every kernel and host source of the library (csrc/**): a tuning result
+    belongs to the code it was timed on."""
+    global _SRC_HASH
+    if _SRC_HASH is None:
+        root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+        h = hashlib.sha256()
+        files = []
+        for d, _, fs in os.walk(root):
+            files += [os.path.join(d, f) for f in fs if f.endswith((".hip", ".hpp", ".cpp", ".h"))]
+        for f in sorted(files, key=lambda x: os.path.relpath(x, root)):
+            h.update(os.path.relpath(f, root).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+        _SRC_HASH = h.hexdigest()[:12]
+    return _SRC_HASH
+
+
 def _arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
@@ -35,7 +58,7 @@ def _cus() -> int:
 
 def shape_key(N, M, E, S, loss, grads: Sequence[str], K: int) -> str:
     kb = 1 << max(0, int(K - 1).bit_length())  # bucket positions by power of two
-    return f"{_arch()}|N{N}|M{M}|E{E}|S{S}|{loss}|{'+'.join(sorted(grads))}|K{kb}"
+    return f"{_arch()}|src{source_hash()}|N{N}|M{M}|E{E}|S{S}|{loss}|{'+'.join(sorted(grads))}|K{kb}"
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, dict]:
@@ -100,11 +123,20 @@ def _time(fn, reps: int) -> float:
 
 
 def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("obj", "probe", "pos"),
-              reps: int = 5, cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True, log=None):
+              reps: int = 5, cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True, log=None,
+              key_K: Optional[int] = None):
     """Pick the fastest parity-passing fused configuration for one plan shape.
-    ``shape`` holds N, M, E, S, H, W, loss, eps, lambda_z. Returns (tune, report)."""
+    ``shape`` holds N, M, E, S, H, W, loss, eps, lambda_z. Returns (tune, report).
+    ``key_K`` looks the choice up under another position count (the full workload's,
+    when fewer of its positions are passed); a choice tuned here on fewer positions is
+    then not stored under that key."""
     K = int(positions.shape[0])
-    key = shape_key(shape["N"], shape["M"], shape["E"], shape["S"], shape["loss"], grads, K)
+    key = shape_key(shape["N"], shape["M"], shape["E"], shape["S"], shape["loss"], grads, key_K or K)
+    if key_K is not None and key_K != K:
+        cache_path = cache_path if use_cache else None
+        store = False
+    else:
+        store = True
     cache = load_cache(cache_path) if (cache_path and use_cache) else {}
     if use_cache and key in cache:
         return cache[key]["tune"], {"key": key, "cached": True}
@@ -137,7 +169,7 @@ def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("
         del plan
     if best is None:
         raise RuntimeError(f"no autotuner candidate passed parity for {key}: {results}")
-    if cache_path:
+    if cache_path and store:
         cache = load_cache(cache_path)
         cache[key] = {"tune": best[0], "ms": best[1], "when": time.strftime("%Y-%m-%d %H:%M:%S"),
                       "candidates": results}

@@ -183,3 +183,76 @@ def covering(prob, ty: int, tx: int, size: int):
     N = prob.N
     hit = (y0 <= ty + size - 1) & (y0 + N >= ty) & (x0 <= tx + size - 1) & (x0 + N >= tx)
     return np.nonzero(hit)[0]
+
+
+def bench_tune(prob, I_meas, grads, key_K=None):
+    """The implementation choice the benchmark runs for this workload shape, looked up
+    exactly as bench.py does (the autotuner's cache for the current sources; a fresh,
+    parity-gated tune when it holds none). ``key_K``: the full workload's position count
+    when ``prob`` carries only some of its positions."""
+    from paper_2510_20929_amd import autotune
+    shape = dict(N=prob.N, M=prob.M, E=prob.E, S=prob.S, H=prob.H, W=prob.W, loss=prob.loss, eps=prob.eps,
+                 lambda_z=prob.lambda_z)
+    w = None if prob.weights is None else dev(prob.weights)
+    tune, rep = autotune.tune_plan(shape, dev(prob.obj), dev(prob.probe), dev(prob.positions), dev(I_meas),
+                                   weights=w, grads=grads, key_K=key_K)
+    print(f"bench tune for {rep['key']}: {tune} ({'cached' if rep.get('cached') else 'tuned now'})", flush=True)
+    return tune
+
+
+def kernel_instance(prob, tune, threads):
+    """Name of the fused kernel instance a plan runs (as the benchmark reports it)."""
+    loss = 1 if prob.loss == "poisson" else 0
+    if prob.N >= 256:
+        return f"fused_big_kernel<{prob.N},{threads},{loss}>"
+    if prob.S > 1:
+        return f"fused_small_ms_kernel<{prob.N},{threads},{loss}>"
+    v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
+    rv = "true" if v in (2, 3, 4) else "false"
+    goreg = "true" if v in (2, 3) else "false"
+    return f"fused_small_kernel<{prob.N},{threads},{loss},{rv},{goreg}>"
+
+
+def _oracle_shard(args):
+    """Worker: the oracle's forward + adjoint over one shard of positions (spawned CPU
+    process that never touches the GPU). Returns the parameter-sized sums and the
+    per-position outputs of the shard."""
+    obj, probe, pos, weights, I, kw = args
+    r = oracle.forward_adjoint(obj, probe, pos, I, weights=weights, **kw)
+    return {k: v for k, v in r.items() if k != "I_pred"}
+
+
+def run_oracle_sharded(prob, I_meas, grads, norm_count=None, workers: int = 16):
+    """``run_oracle`` over all positions of a full-size workload, split into shards run in
+    parallel CPU processes with the global normaliser: the loss, object and probe
+    gradients are the sums over the shards (the data-parallel identity the oracle's
+    shard-sum pin checks), position and weight gradients the concatenation."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import time
+    K = prob.K
+    n = max(1, min(workers, os.cpu_count() or 1))
+    pieces = max(1, min(4 * n, K // 4))
+    bounds = np.linspace(0, K, pieces + 1).astype(int)
+    kw = dict(loss=prob.loss, eps=prob.eps, lambda_z=prob.lambda_z, norm_count=norm_count or K, grads=grads)
+    jobs = [(prob.obj, prob.probe, prob.positions[a:b], None if prob.weights is None else prob.weights[a:b],
+             I_meas[a:b], kw) for a, b in zip(bounds[:-1], bounds[1:])]
+    parts = [None] * len(jobs)
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn")) as ex:
+        futs = {ex.submit(_oracle_shard, j): i for i, j in enumerate(jobs)}
+        for done, f in enumerate(cf.as_completed(futs), 1):
+            parts[futs[f]] = f.result()
+            if done % max(1, len(jobs) // 8) == 0 or done == len(jobs):
+                print(f"sharded oracle: {done}/{len(jobs)} shards, {time.time() - t0:.0f} s", flush=True)
+    out = {"loss": sum(p["loss"] for p in parts)}
+    for key in ("g_obj", "g_probe"):
+        if key in parts[0]:
+            acc = parts[0][key].copy()
+            for p in parts[1:]:
+                acc += p[key]
+            out[key] = acc
+    for key in ("g_pos", "g_weights"):
+        if key in parts[0]:
+            out[key] = np.concatenate([p[key] for p in parts], axis=0)
+    return out

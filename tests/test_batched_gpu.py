@@ -94,3 +94,21 @@ def test_batched_per_step_mode(batch_case):
         p, I = starts[i], meas[i]
         ref = oracle.forward_adjoint(p.obj, p.probe, p.positions, I, weights=p.weights, loss=p.loss, grads=GRADS)
         compare(_np(outs[j]), ref, GRADS, tag=f"batched plain {p.name}")
+
+
+def test_batched_small_grid_vs_oracle(batch_case):
+    """The batched launch on 8 workgroups per frame-size class (split among the class's
+    datasets by work): the larger datasets give each of their workgroups several
+    positions (ragged tails), so the per-workgroup probe-gradient accumulation of each
+    class's body is compared with the oracle."""
+    torch = torch_cuda()
+    from paper_2510_20929_amd import Batch
+    starts, meas = batch_case
+    b = Batch(starts, tune={"grid": 8})
+    outs = [b.bind(i, *_tensors(p, I)[:4], weights=_tensors(p, I)[4]) for i, (p, I) in enumerate(zip(starts, meas))]
+    b.launch(GRADS)
+    torch.cuda.synchronize()
+    assert b.get_error() == 0
+    for i, (p, I) in enumerate(zip(starts, meas)):
+        ref = oracle.forward_adjoint(p.obj, p.probe, p.positions, I, weights=p.weights, loss=p.loss, grads=GRADS)
+        compare(_np(outs[i]), ref, GRADS, tag=f"batched grid=8 {p.name} N={p.N} M={p.M} K={p.K}")

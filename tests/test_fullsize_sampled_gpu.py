@@ -80,7 +80,13 @@ def _shard_sum(plan, args, w, grads, K, tag):
 
 
 def test_config2_full_sampled():
+    """Config 2 at full size (10000 positions, 8 eigenprobes of 256^2) on the instance the
+    benchmark runs: the loss, the whole eigenprobe gradient, every position's weight and
+    position gradients against the oracle summed over position shards (parallel CPU
+    processes, global normaliser); predicted intensities of sampled positions and
+    object-gradient tiles against the oracle on the positions that touch them."""
     torch_cuda()
+    from gpu_util import bench_tune, run_oracle_sharded
     from paper_2510_20929_amd import Plan
     truth = W.make_config(2)
     start = W.perturb(truth, 5)
@@ -89,8 +95,17 @@ def test_config2_full_sampled():
     tiles = [(1000, 1000, 8), (300, 1700, 8)]
     I = measured_sparse([truth], [_needed(start, ks, tiles)], [6])[0]
     grads = ("obj", "probe", "weights", "pos")
-    plan = Plan.for_problem(start, norm_count=start.K)
+    tune = bench_tune(start, I, start.grads)
+    plan = Plan.for_problem(start, norm_count=start.K, tune=tune)
     out, args, w = _full_launch(plan, start, I, grads)
+    ref = run_oracle_sharded(start, I, ("probe", "weights", "pos"))
+    e = abs(float(out["loss"].cpu()[0]) - ref["loss"]) / abs(ref["loss"])
+    print(f"c2 full {tune} loss (all positions): {e:.2e}", flush=True)
+    assert e <= FWD_TOL
+    for key in ("g_probe", "g_weights", "g_pos"):
+        e = rel_l2(out[key].cpu().numpy(), ref[key])
+        print(f"c2 full {key} (all positions): {e:.2e}", flush=True)
+        assert e <= GRAD_TOL
     _sampled_checks(start, I, grads, out, ks, tiles, "c2 full")
     _shard_sum(plan, args, w, grads, start.K, "c2 full")
 
@@ -106,15 +121,17 @@ def c3_inputs():
     return start, measured_sparse([truth], [_needed(start, ks, C3_TILES)], [6])[0], ks
 
 
-@pytest.mark.parametrize("recompute", [0, 1], ids=["store", "recompute"])
+@pytest.mark.parametrize("recompute", [0, 1, "bench"], ids=["store", "recompute", "bench-choice"])
 def test_config3_full_sampled(recompute, c3_inputs):
     torch_cuda()
+    from gpu_util import bench_tune
     from paper_2510_20929_amd import Plan
     start, I, ks = c3_inputs
     grads = ("obj", "probe", "pos")
-    plan = Plan.for_problem(start, norm_count=start.K, tune={"recompute": recompute})
+    tune = bench_tune(start, I, start.grads) if recompute == "bench" else {"recompute": recompute}
+    plan = Plan.for_problem(start, norm_count=start.K, tune=tune)
     out, args, w = _full_launch(plan, start, I, grads)
-    _sampled_checks(start, I, grads, out, ks, C3_TILES, f"c3 full {recompute}")
+    _sampled_checks(start, I, grads, out, ks, C3_TILES, f"c3 full {tune}")
     if recompute == 0:
         _shard_sum(plan, args, w, grads, start.K, "c3 full")
 
@@ -133,6 +150,11 @@ def test_config4_full_batched_vs_per_call_and_sampled():
         seen.add(s.N)
         ty = int(s.positions[s.K // 2, 0])
         picks[i] = (np.sort(rng.choice(s.K, min(3, s.K), replace=False)), (ty, ty, 8))
+    # whole-dataset oracle runs: the dataset with the fewest positions of each frame size
+    whole = {}
+    for i, s in enumerate(starts):
+        if s.N not in whole or s.K < starts[whole[s.N]].K:
+            whole[s.N] = i
     needs = [_needed(s, *((picks[i][0], [picks[i][1]]) if i in picks else (np.arange(min(8, s.K)), [])))
              for i, s in enumerate(starts)]
     Is = measured_sparse(truths, needs, [4 + i for i in range(len(truths))])
@@ -162,3 +184,14 @@ def test_config4_full_batched_vs_per_call_and_sampled():
         e = rel_l2(batched[i]["g_obj"][:, ty:ty + sz, tx:tx + sz].cpu().numpy(), r["g_obj"][:, ty:ty + sz, tx:tx + sz])
         print(f"c4 dataset {i} g_obj tile ({len(idx)} positions): {e:.2e}", flush=True)
         assert e <= GRAD_TOL
+    from gpu_util import run_oracle_sharded
+    for N, i in sorted(whole.items()):
+        s = starts[i]
+        ref = run_oracle_sharded(s, Is[i], ("probe", "pos", "weights"))
+        e = abs(float(batched[i]["loss"].cpu()[0]) - ref["loss"]) / abs(ref["loss"])
+        print(f"c4 dataset {i} (N={N}, M={s.M}, K={s.K}) loss (all positions): {e:.2e}", flush=True)
+        assert e <= FWD_TOL
+        for key in ("g_probe", "g_pos", "g_weights"):
+            e = rel_l2(batched[i][key].cpu().numpy(), ref[key])
+            print(f"c4 dataset {i} (N={N}) {key} (all positions): {e:.2e}", flush=True)
+            assert e <= GRAD_TOL

@@ -64,3 +64,44 @@ def test_rejects_in_place():
     pr = dev(p.probe)
     with pytest.raises(PtyhipError):
         plan.orthogonalize_modes(pr, out=pr)
+
+
+def test_orthogonalize_degenerate_spectrum():
+    """A Gram matrix with a repeated eigenvalue: the eigenmodes of the repeated value are
+    not unique (any orthonormal basis of their span is correct), so the result is checked
+    by what defines it: the new modes are orthogonal with the Gram eigenvalues as powers,
+    the strongest mode matches the oracle (unique up to the phase convention), the pair
+    spans the same subspace as the oracle's pair, the mode-summed intensity is unchanged
+    at every pixel and so is the loss."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(66)
+    N, M = 32, 3
+    B = rng.normal(size=(M, N * N)) + 1j * rng.normal(size=(M, N * N))
+    Q, _ = np.linalg.qr(B.T)                                   # orthonormal columns
+    base = (Q.T * np.sqrt([50.0, 20.0, 20.0])[:, None]).reshape(M, N, N)   # powers 50, 20, 20
+    V, _ = np.linalg.qr(rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M)))
+    U = np.einsum("jm,mab->jab", V, base)[None].astype(np.complex64)       # mixed: Gram not diagonal
+    p = W.Problem("degenerate", np.ones((1, 3 * N, 3 * N), np.complex64), U,
+                  rng.uniform(0, 2 * N - 2, size=(12, 2)).astype(np.float32), None, "amplitude")
+    plan, out, powers = _run(p)
+    got = out.cpu().numpy().astype(np.complex128)[0].reshape(M, -1)
+    G = got.conj() @ got.T
+    off = np.abs(G - np.diag(np.diag(G))).max() / np.abs(np.diag(G)).max()
+    print(f"degenerate: off-diagonal {off:.2e}, powers {powers}", flush=True)
+    assert off < 1e-5
+    assert rel_l2(powers, [50.0, 20.0, 20.0]) <= 1e-5
+    assert rel_l2(np.real(np.diag(G)), powers) <= 1e-5
+    ref, lam = oracle.orthogonalize_modes(U)
+    ref = ref[0].reshape(M, -1)
+    assert rel_l2(got[0], ref[0]) <= 1e-5                     # the non-degenerate mode
+    # the degenerate pair spans the oracle pair's subspace
+    Qr, _ = np.linalg.qr(ref[1:].T)
+    resid = got[1:].T - Qr @ (Qr.conj().T @ got[1:].T)
+    assert np.linalg.norm(resid) <= 1e-5 * np.linalg.norm(got[1:])
+    I0 = np.sum(np.abs(U[0].astype(np.complex128)) ** 2, axis=0)
+    I1 = np.sum(np.abs(got.reshape(M, N, N)) ** 2, axis=0)
+    assert rel_l2(I1, I0) <= 1e-5
+    Im = rng.uniform(0, 50, size=(12, N, N)).astype(np.float32)
+    l0 = float(plan.forward(dev(p.obj), dev(U), dev(p.positions), dev(Im))[0])
+    l1 = float(plan.forward(dev(p.obj), out, dev(p.positions), dev(Im))[0])
+    assert abs(l1 - l0) <= FWD_TOL * abs(l0)

@@ -17,16 +17,30 @@ def _plan(prob, **kw):
     return Plan.for_problem(prob, **kw)
 
 
-@pytest.mark.parametrize("form", ["store", "recompute", "plain"])
+TUNES = {"store": None, "recompute": {"recompute": 1},
+         "fused_small_ms_kernel<128,1024,0>-store": {"variant": 1, "grid": 16},
+         "fused_small_ms_kernel<128,1024,0>-recompute": {"variant": 1, "recompute": 1, "grid": 16},
+         "fused_small_ms_kernel<128,512,0>-grid16": {"variant": 0, "grid": 16},
+         "bench-choice": "bench", "plain": None}
+
+
+@pytest.mark.parametrize("form", list(TUNES))
 def test_config3_reduced(form):
     """Config 3 structure (128^2, 2 modes, weak-phase slices, lambda z = 81.92 px^2,
-    spiral scan, object/probe/position gradients) with 3 slices of 300^2 and 90 positions."""
+    spiral scan, object/probe/position gradients) with 3 slices of 300^2 and 90 positions.
+    The forms with 16 workgroups give each workgroup five or six positions (ragged tail);
+    bench-choice is the instance the benchmark runs for the full 5000-position workload,
+    also on 16 workgroups."""
     start, I = case(3, H=300, K=90, S=3)
     grads = ("obj", "probe", "pos")
     ref = run_oracle(start, I, grads)
-    plan = _plan(start, tune={"recompute": 1} if form == "recompute" else None)
+    tune = TUNES[form]
+    if tune == "bench":
+        from gpu_util import bench_tune
+        tune = dict(bench_tune(start, I, grads, key_K=5000), grid=16)
+    plan = _plan(start, tune=tune)
     got = run_gpu(plan, start, I, grads, plain=(form == "plain"))
-    compare(got, ref, grads, tag=f"c3 {form}")
+    compare(got, ref, grads, tag=f"c3 {form} {tune}")
     assert got["flags"] == 0
 
 

@@ -112,13 +112,30 @@ def test_forward_only(N, M, E):
 @pytest.mark.parametrize("N", [64, 128])
 def test_fused_variants(N, variant, recompute):
     """Every thread layout of the on-chip fused kernel (scratch- or register-resident
-    patch), storing or recomputing the far fields, against the oracle."""
-    start, I = custom_problem(300 + N + 10 * variant + recompute, N, 3, 2, 1, N * 3, 90, loss="poisson",
+    patch), storing or recomputing the far fields, against the oracle, on a grid of 16
+    workgroups: each workgroup takes five or six of the 90 positions (ragged tail), so
+    its probe-gradient accumulator and the patch-gradient frames carry over from one
+    position to the next. Four modes at 128^2 (the benchmark's shape), three at 64^2."""
+    M = 4 if N == 128 else 3
+    start, I = custom_problem(300 + N + 10 * variant + recompute, N, M, 2, 1, N * 3, 90, loss="poisson",
                               weights="opr")
     grads = ("obj", "probe", "pos", "weights")
     ref = run_oracle(start, I, grads)
-    got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute}), start, I, grads)
-    compare(got, ref, grads, tag=f"N={N} variant={variant} recompute={recompute}")
+    got = run_gpu(_plan(start, tune={"variant": variant, "recompute": recompute, "grid": 16}), start, I, grads)
+    compare(got, ref, grads, tag=f"N={N} M={M} variant={variant} recompute={recompute} grid=16")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("recompute", [0, 1])
+def test_fused_variants_single_eigenprobe(recompute):
+    """The benchmark's headline instance (128^2, 1024 threads, patch in registers, patch
+    gradient in scratch) with one unweighted eigenprobe and four modes, Poisson loss, on
+    16 workgroups with a ragged tail (the weight-free probe loops of the headline workload)."""
+    start, I = custom_problem(377 + recompute, 128, 4, 1, 1, 400, 75, loss="poisson")
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": 4, "recompute": recompute, "grid": 16}), start, I, grads)
+    compare(got, ref, grads, tag=f"headline layout recompute={recompute} grid=16")
     assert got["flags"] == 0
 
 
@@ -163,4 +180,24 @@ def test_config5_mode_heavy(plain):
     ref = run_oracle(start, I, grads)
     got = run_gpu(_plan(start), start, I, grads, plain=plain)
     compare(got, ref, grads, tag=f"c5 {'plain' if plain else 'fused'}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("which", ["bench-choice", "fused_small_kernel<128,1024,0,true,false>-recompute"])
+def test_config5_tuned_instance(which):
+    """Config 5 (30 modes) on the instance the benchmark runs for its full 6732-position
+    workload (the autotuner's cached choice) and on the 1024-thread register-patch layout
+    with recomputed far fields, on 16 workgroups so that each takes three of the 48
+    positions."""
+    from gpu_util import bench_tune
+    start, I = case(5, K=48)
+    grads = ("obj", "probe", "pos")
+    if which == "bench-choice":
+        tune = dict(bench_tune(start, I, grads, key_K=6732))
+    else:
+        tune = {"variant": 4, "recompute": 1}
+    tune["grid"] = 16
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune=tune), start, I, grads)
+    compare(got, ref, grads, tag=f"c5 {which} {tune}")
     assert got["flags"] == 0
