@@ -22,7 +22,10 @@ import torch
 
 from .ptyhip import Batch, Plan
 
-DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+# the frozen cache shipped with the package; PTYHIP_TUNE_CACHE points every lookup and
+# every new result at another file (for a retuning run)
+DEFAULT_CACHE = (os.environ.get("PTYHIP_TUNE_CACHE")
+                 or os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
 FWD_TOL = 1e-5
 GRAD_TOL = 1e-4
 
