@@ -241,16 +241,26 @@ def apply_A(obj, probe, positions, weights=None, lambda_z: float = 0.0) -> np.nd
 
 
 def _backward_one(O, U, w_k, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
-                  gO, gU, want_w: bool, subpixel="bilinear"):
+                  gO, gU, want_w: bool, subpixel="bilinear", q2=None):
     """Adjoint of one position given dL/dPsi (g convention) for every mode.
-    Accumulates into gO, gU; returns (per-slice patch gradients, dL/dw_k)."""
+    Accumulates into gO, gU; returns (per-slice patch gradients, dL/dw_k, dL/d(lambda z)).
+
+    q2 (fy^2 + fx^2 on the unshifted grid) asks for the slice-spacing gradient: psi_s =
+    F^-1(H F chi_{s-1}) with H = exp(-i pi lz q2), so d psi_s / d lz = F^-1((-i pi q2) H F
+    chi_{s-1}) and, F being unitary, dL/dlz = sum_{s>0} Re sum_f conj(F g_psi_s) (-i pi q2)
+    H F chi_{s-1}, with g_psi_s the gradient of the incident wave of slice s."""
     S = O.shape[0]
     g = ifft2u(gPsi)                                # [M, N, N] gradient of the last exit wave
     g_patch = [None] * S
+    g_lz = 0.0
     for s in range(S - 1, -1, -1):
         g_patch[s] = np.sum(np.conj(psis[s]) * g, axis=0)
         g_psi = np.conj(patches[s])[None] * g       # gradient of the incident wave psi_s
         if s > 0:
+            if q2 is not None:
+                Gs = fft2u(g_psi)
+                HX = tf * fft2u(psis[s - 1] * patches[s - 1][None])
+                g_lz += float(np.sum(np.real(np.conj(Gs) * (-1j * math.pi * q2) * HX)))
             g = propagate_adjoint(g_psi, tf)
         else:
             g = g_psi
@@ -265,7 +275,7 @@ def _backward_one(O, U, w_k, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
     scat = fourier_scatter if subpixel == "fourier" else scatter_patch
     for s in range(S):
         scat(gO[s], g_patch[s], y0, x0, fy, fx)
-    return g_patch, gw
+    return g_patch, gw, g_lz
 
 
 def apply_AH(Y, obj, probe, positions, weights=None, lambda_z: float = 0.0):
@@ -302,7 +312,13 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
                     grads: Sequence[str] = ("obj", "probe"),
                     det_lambda_z: Optional[float] = None, subpixel: str = "bilinear") -> Dict[str, np.ndarray]:
     """Loss, predicted intensity and the requested gradients
-    (any of "obj", "probe", "pos", "weights", and "lambda_z" in the near field).
+    (any of "obj", "probe", "pos", "weights", and "lambda_z").
+
+    "lambda_z" is the gradient with respect to the wavelength-distance product of the
+    model's Fresnel propagator: the slice spacing lambda_z of a multislice model (S > 1,
+    far field; the slice spacing is a refinable parameter of the automatic-differentiation
+    reconstructor, Reconstructors) or det_lambda_z of the near-field detector (S = 1). A
+    model with neither, or with both, has no single lambda_z to differentiate (ValueError).
 
     Near field (det_lambda_z given; the propagation variant of the forward model, Software
     design, Overview): the last exit wave chi is carried to the detector by Fresnel
@@ -327,8 +343,15 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
     want_pos = "pos" in grads
     want_w = "weights" in grads
     want_lz = "lambda_z" in grads
-    if want_lz and not near:
-        raise ValueError("the lambda_z gradient belongs to the near-field model")
+    if want_lz and near and S > 1:
+        raise ValueError("lambda_z is ambiguous with both slices and a near-field detector")
+    if want_lz and not near and S == 1:
+        raise ValueError("a single-slice far-field model has no lambda_z")
+    slice_lz = want_lz and S > 1
+    if slice_lz:
+        fq = np.fft.fftfreq(N)
+        q2_slices = fq[:, None] ** 2 + fq[None, :] ** 2
+        g_lz = 0.0
     any_grad = len(grads) > 0
     if near:
         tf_det = fresnel_tf(N, float(det_lambda_z))
@@ -364,8 +387,10 @@ def forward_adjoint(obj, probe, positions, I_meas, *, weights=None, loss: str = 
             if want_lz:
                 g_lz += float(np.sum(np.real(np.conj(Gd) * (-1j * math.pi * q2) * tf_det * X)))
             gPsi = np.conj(tf_det) * Gd               # far-field-domain gradient of chi
-        g_patch, gwk = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
-                                     gO, gU, want_w, subpixel)
+        g_patch, gwk, glz = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx,
+                                          gO, gU, want_w, subpixel, q2_slices if slice_lz else None)
+        if slice_lz:
+            g_lz += glz
         if want_w:
             gw[k] = gwk
         if want_pos:
@@ -424,7 +449,7 @@ def patch_gradients(obj, probe, positions, I_meas, *, weights=None, loss="amplit
         gPsi = (2.0 / (Kn * N * N)) * c[None] * Psi
         gO = np.zeros_like(O)
         gU = np.zeros_like(U)
-        g_patch, _ = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx, gO, gU, False)
+        g_patch, _, _ = _backward_one(O, U, wk, P, patches, psis, gPsi, tf, y0, x0, fy, fx, gO, gU, False)
         for s in range(S):
             out[k, s] = g_patch[s]
     return out
