@@ -74,7 +74,9 @@ enum {
   PTYHIP_ACCUMULATE = 16,   /* add into the outputs (and loss) instead of overwriting */
   PTYHIP_PLAIN = 32,        /* run the per-step kernels instead of the fused kernel */
   PTYHIP_BATCH_PER_CALL = 64, /* batch only: one non-captured fused call per dataset */
-  PTYHIP_GRAD_LAMBDA_Z = 128  /* near field: dL/d(det_lambda_z), device double[1] */
+  PTYHIP_GRAD_LAMBDA_Z = 128  /* dL/d(lambda z) of the plan's Fresnel propagator, device double[1]:
+                                 det_lambda_z (near field) or the slice spacing lambda_z
+                                 (several slices); fused form only */
 };
 
 /* sub-pixel patch model (Software design, Overview: patch extraction is a shared routine;
@@ -186,10 +188,18 @@ ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, 
                                      const float* I_meas, double* loss, float* I_pred, float* g_obj,
                                      float* g_probe, float* g_pos, float* g_weights);
 
-/* As ptyhip_forward_adjoint, plus the near-field gradient with respect to det_lambda_z
- * (PTYHIP_GRAD_LAMBDA_Z; device double[1], overwritten or accumulated like the loss):
- * dL/d(lz) = sum_k,m Re sum_f conj(F g_Psi) (-i pi (fy^2 + fx^2)) H F chi, by the chain
- * rule through the propagator. The flag requires a near-field plan. */
+/* As ptyhip_forward_adjoint, plus (PTYHIP_GRAD_LAMBDA_Z) the gradient with respect to the
+ * wavelength-distance product of the plan's Fresnel propagator H = exp(-i pi lz (fy^2 +
+ * fx^2)), by the chain rule through the propagator, in g_lambda_z (device double[1],
+ * overwritten or accumulated like the loss):
+ *   - near-field plan: lz = det_lambda_z (Software design, Overview: the near-field
+ *     propagation option), dL/dlz = sum_k,m Re sum_f conj(F g_Psi) (-i pi q^2) H F chi;
+ *   - multislice plan (S > 1): lz = the slice spacing lambda_z (Sec. 2.1 multislice; the
+ *     automatic-differentiation reconstructor refines the slice spacing, Reconstructors),
+ *     dL/dlz = sum_k,m sum_{s>0} Re sum_f conj(F g_psi_s) (-i pi q^2) F psi_s, with
+ *     psi_s the incident wave of slice s and g_psi_s its gradient.
+ * The flag with a single-slice far-field plan, or with a NULL g_lambda_z, is EINVAL;
+ * with PTYHIP_PLAIN it is EUNSUPPORTED (the fused kernels compute it). */
 ptyhip_status ptyhip_forward_adjoint_ex(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
                                         const float* probe, const float* weights, const float* positions,
                                         const float* I_meas, double* loss, float* I_pred, float* g_obj,

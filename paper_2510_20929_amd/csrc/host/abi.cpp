@@ -109,7 +109,9 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
-  if (d.propagation == PTYHIP_PROP_NEAR && (st = dalloc(p, &p->lz_part, kk)) != PTYHIP_OK) return st;
+  // per-position partials of dL/d(lambda z): the detector distance of the near field or
+  // the slice spacing of a multislice model
+  if ((d.propagation == PTYHIP_PROP_NEAR || S > 1) && (st = dalloc(p, &p->lz_part, kk)) != PTYHIP_OK) return st;
   p->copies = 1;
   p->probe_elems = size_t(E) * M * NN;
   if ((st = dalloc(p, &p->gprobe_part, p->probe_elems)) != PTYHIP_OK) return st;
@@ -387,8 +389,11 @@ ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flag
   const bool want_w = !forward_only && (flags & PTYHIP_GRAD_WEIGHTS);
   const bool near = d.propagation == PTYHIP_PROP_NEAR;
   const bool want_lz = !forward_only && (flags & PTYHIP_GRAD_LAMBDA_Z);
-  if (want_lz && (!near || !g_lz)) return PTYHIP_EINVAL;
+  // lambda z of the plan's propagator: the detector distance (near field) or the slice
+  // spacing (several slices); a single-slice far-field plan has none
+  if (want_lz && (!(near || d.n_slices > 1) || !g_lz)) return PTYHIP_EINVAL;
   if ((near || d.subpixel == PTYHIP_SUBPIXEL_FOURIER) && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
+  if (want_lz && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;
   if (want_pos && K > 0 && !g_pos) return PTYHIP_EINVAL;

@@ -21,7 +21,12 @@ __global__ __launch_bounds__(T) void fused_small_near_kernel(CallArgs a) {
 // Scratch per workgroup (element i of thread t at i*T + t):
 //   patches [S][NN], patch gradients [S][NN], incident waves [M][S][NN] (unless
 //   recomputed), probe-gradient accumulator [E][M][NN] at pacc_off.
-template <int N, int T, int LOSS>
+// LZ: also the gradient with respect to the slice spacing lambda_z. The incident wave of
+// slice s > 0 is psi_s = F^-1(H F chi_{s-1}), H = exp(-i pi lz q^2), so its derivative is
+// F^-1((-i pi q^2) F psi_s) and dL/dlz = sum_{s>0} Re sum_f conj(F g_psi_s) (-i pi q^2)
+// F psi_s, g_psi_s being the gradient of the incident wave that the back-propagation
+// transforms anyway: one more transform (of psi_s) per slice and mode.
+template <int N, int T, int LOSS, bool LZ>
 __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   using F = Frame2D<N, T>;
   using C = SmallCtx<N, T>;
@@ -80,6 +85,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
     if (!p.ok) {
       skip_position<N, T>(a, k, p);
+      if (LZ && tid == 0) a.lz_part[k] = 0.0;
       continue;
     }
     __syncthreads();
@@ -87,6 +93,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
     if (tid < MAX_EIG) wacc[tid] = 0.0;
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
+    double lz = 0.0;
 
     for (int s = 0; s < S; ++s) {
       float2* o = Op + size_t(s) * FR;
@@ -137,7 +144,10 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
         }
       }
       if (a.mode == MODE_APPLY_A) continue;
-      if (!position_loss<N, T, LOSS>(a, k, cf, red)) continue;
+      if (!position_loss<N, T, LOSS>(a, k, cf, red)) {
+        if (LZ && tid == 0) a.lz_part[k] = 0.0;
+        continue;
+      }
       if (a.mode == MODE_FORWARD) continue;
     }
 
@@ -186,11 +196,23 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
         }
         if (s > 0) {
           F::forward(v, lds, tws, inv_n);
+          if constexpr (LZ) {
+            // v = F g_psi_s; ps becomes F psi_s = H F chi_{s-1}
+            F::forward(ps, lds, tws, inv_n);
+            const int t2 = opaque_tid();
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+              lz += double(3.14159265358979323846f * C::d_q2(t2, i) * (v[i].x * ps[i].y - v[i].y * ps[i].x));
+          }
           apply_tf(v, true);
           F::inverse(v, lds, tws, inv_n);
         }
       }
       probe_gradients<N, T>(a, m, wk, v, sbf, int(a.pacc_off * sizeof(float2)), red, wacc);
+    }
+    if constexpr (LZ) {
+      const double tot = block_sum<T>(lz, red);
+      if (tid == 0) a.lz_part[k] = tot;
     }
 
     double gy = 0.0, gx = 0.0;
@@ -255,13 +277,20 @@ static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
     else hipLaunchKernelGGL((fused_small_near_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
     return hipGetLastError();
   }
-  if (a.loss == 0) {
-    if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
-  } else {
-    if (ms) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
-    else hipLaunchKernelGGL((fused_small_kernel<N, T, 1, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
+  if (ms) {
+    // the slice-spacing gradient needs the adjoint and its per-position partials
+    const bool lz = (a.want & WANT_LZ) && a.mode == MODE_FWD_ADJ && a.lz_part != nullptr;
+    if (a.loss == 0) {
+      if (lz) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0, true>), dim3(grid), dim3(T), 0, st, a);
+      else hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 0, false>), dim3(grid), dim3(T), 0, st, a);
+    } else {
+      if (lz) hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1, true>), dim3(grid), dim3(T), 0, st, a);
+      else hipLaunchKernelGGL((fused_small_ms_kernel<N, T, 1, false>), dim3(grid), dim3(T), 0, st, a);
+    }
+    return hipGetLastError();
   }
+  if (a.loss == 0) hipLaunchKernelGGL((fused_small_kernel<N, T, 0, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
+  else hipLaunchKernelGGL((fused_small_kernel<N, T, 1, RV, GOREG>), dim3(grid), dim3(T), 0, st, a);
   return hipGetLastError();
 }
 

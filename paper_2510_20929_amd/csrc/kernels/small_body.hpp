@@ -50,6 +50,14 @@ struct SmallCtx {
     const int l = i / N2, ii = i % N2;
     return centred_index(F::d_ky(t, l, ii), F::d_kx(t, l), N);
   }
+  // fy^2 + fx^2 (cycles per pixel) of element i in layout D: the phase of the Fresnel
+  // transfer function exp(-i pi lz q^2) per unit lz
+  __device__ __forceinline__ static float d_q2(int t, int i) {
+    const int l = i / N2, ii = i % N2;
+    const int ky = F::d_ky(t, l, ii), kx = F::d_kx(t, l);
+    const float fy = float(ky < N / 2 ? ky : ky - N) / float(N), fx = float(kx < N / 2 ? kx : kx - N) / float(N);
+    return fy * fy + fx * fx;
+  }
 };
 
 // Calls f(i, P) for the thread's elements i (layout A) with P = the probe of mode m at
@@ -587,13 +595,6 @@ __device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N
   constexpr int X_B = 2 * C::NN * 8;
   const int pacc_b = int(a.pacc_off * sizeof(float2));
   if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
-  // frequency of element i in layout D, cycles per pixel, squared
-  auto q2 = [&](int t, int i) {
-    const int l = i / C::N2, ii = i % C::N2;
-    const int ky = F::d_ky(t, l, ii), kx = F::d_kx(t, l);
-    const float fy = float(ky < N / 2 ? ky : ky - N) * inv_n, fx = float(kx < N / 2 ? kx : kx - N) * inv_n;
-    return fy * fy + fx * fx;
-  };
 
   for (int k = wg; k < a.K; k += nwg) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -664,7 +665,7 @@ __device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N
           const float2 h = a.tfd[C::d_freq(t, i)];
           if (want_lz) {
             const float2 z = cmul(h, sb.ld(t * 8, xb + i * T * 8));
-            lz += double(3.14159265358979323846f * q2(t, i) * (v[i].x * z.y - v[i].y * z.x));
+            lz += double(3.14159265358979323846f * C::d_q2(t, i) * (v[i].x * z.y - v[i].y * z.x));
           }
           v[i] = cmulc(h, v[i]);
         }

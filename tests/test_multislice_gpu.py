@@ -53,3 +53,43 @@ def test_multislice_small(N, S, M, E):
     for plain in (False, True):
         got = run_gpu(_plan(start), start, I, grads, plain=plain)
         compare(got, ref, grads, tag=f"ms N={N} S={S} {'plain' if plain else 'fused'}")
+
+
+@pytest.mark.parametrize("tune", [None, {"recompute": 1}, {"variant": 1, "grid": 16},
+                                  {"variant": 1, "recompute": 1, "grid": 16}],
+                         ids=["store", "recompute", "1024-store-grid16", "1024-recompute-grid16"])
+def test_slice_spacing_gradient(tune):
+    """dL/d(lambda z) of the slice spacing (with every other gradient) against the oracle,
+    config 3 structure with 3 slices, stored or recomputed incident waves."""
+    start, I = case(3, H=300, K=90, S=3)
+    grads = ("obj", "probe", "pos", "lambda_z")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune=tune), start, I, grads)
+    compare(got, ref, grads, tag=f"c3 slice lambda_z {tune}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("N,S,M,E,loss", [(32, 2, 1, 1, "poisson"), (64, 4, 2, 2, "amplitude")])
+def test_slice_spacing_gradient_small(N, S, M, E, loss):
+    start, I = custom_problem(330 + N + S, N, M, E, S, N * 3, 60, lz=N / 8.0, loss=loss,
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "lambda_z") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start), start, I, grads)
+    compare(got, ref, grads, tag=f"ms lambda_z N={N} S={S} M={M} E={E}")
+
+
+def test_slice_spacing_gradient_errors():
+    import torch
+    from paper_2510_20929_amd import PtyhipError
+    from gpu_util import dev
+    start, I = custom_problem(341, 32, 1, 1, 2, 100, 10, lz=3.0)
+    plan = _plan(start)
+    args = (dev(start.obj), dev(start.probe), dev(start.positions), dev(I))
+    with pytest.raises(PtyhipError):
+        plan.forward_adjoint(*args, grads=("obj", "lambda_z"), plain=True)   # fused form only
+    single, I1 = custom_problem(342, 32, 1, 1, 1, 100, 10)
+    with pytest.raises(PtyhipError):
+        _plan(single).forward_adjoint(dev(single.obj), dev(single.probe), dev(single.positions), dev(I1),
+                                      grads=("lambda_z",))                     # no propagator
+    torch.cuda.synchronize()
