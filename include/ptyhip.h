@@ -270,6 +270,32 @@ ptyhip_status ptyhip_get_error(ptyhip_plan plan, void* stream, uint32_t* flags);
 /* Clear the latch (asynchronously on `stream`). */
 ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ptyhip_forward_adjoint without a plan.
+ * It runs the same fused on-chip kernels; every buffer beyond the caller's inputs and
+ * outputs (twiddles, per-workgroup frames and probe-gradient accumulators, per-position
+ * partial sums, window gradients, the error latch) is carved out of one file-scope
+ * device array of 128 MiB that each GPU the library runs on holds until the process
+ * ends. The call allocates nothing: no hipMalloc, no hipFree, no allocating library
+ * routine. Positions are processed in chunks that fit the array, with as many
+ * persistent workgroups as fit beside them (at most one per CU, or tune->grid).
+ *   desc, tune   problem and implementation choice as for ptyhip_plan_create_ex (tune
+ *                may be NULL); N <= 128, one slice, far field (bilinear or Fourier-shift
+ *                patch), else PTYHIP_EUNSUPPORTED
+ *   other args   as ptyhip_forward_adjoint (device pointers owned by the caller);
+ *                PTYHIP_PLAIN is EUNSUPPORTED, PTYHIP_GRAD_LAMBDA_Z is EINVAL
+ *   err_flags    device uint32[1] or NULL: receives this call's error latch
+ *                (PTYHIP_FLAG_*; the latch is cleared at the start of every call)
+ * PTYHIP_ENOMEM means that one workgroup's frames plus one position's buffers exceed the
+ * array (for example N = 128 with very many modes times eigenprobes). Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents: calls that overlap on
+ * one GPU (other streams or threads) race and must be serialised by the caller. */
+ptyhip_status ptyhip_forward_adjoint_static(const ptyhip_desc* desc, const ptyhip_tune* tune, void* stream,
+                                            int32_t K, uint32_t flags, const float* obj, const float* probe,
+                                            const float* weights, const float* positions, const float* I_meas,
+                                            double* loss, float* I_pred, float* g_obj, float* g_probe, float* g_pos,
+                                            float* g_weights, uint32_t* err_flags);
+
 /* Many independent reconstructions of uneven frame sizes in one persistent launch per
  * frame size (64^2, 128^2, 256^2, 512^2), captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
  * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. */

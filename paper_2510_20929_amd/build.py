@@ -26,6 +26,7 @@ SOURCES = [
     "kernels/batched.hip",
     "kernels/illum.hip",
     "kernels/modes.hip",
+    "kernels/static_scratch.hip",
     "host/abi.cpp",
     "host/batch.cpp",
 ]

@@ -28,6 +28,7 @@ PROP_FAR, PROP_NEAR = 0, 1
 FLAG_BOUNDS = 1
 FLAG_NONFINITE = 2
 
+OK, EINVAL, ESHAPE, EBOUNDS, ENONFINITE, EHIP, ENOMEM, EUNSUPPORTED = range(8)
 STATUS = {0: "PTYHIP_OK", 1: "PTYHIP_EINVAL", 2: "PTYHIP_ESHAPE", 3: "PTYHIP_EBOUNDS", 4: "PTYHIP_ENONFINITE",
           5: "PTYHIP_EHIP", 6: "PTYHIP_ENOMEM", 7: "PTYHIP_EUNSUPPORTED"}
 
@@ -38,7 +39,7 @@ EXPORTED = [
     "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients",
     "ptyhip_orthogonalize_modes", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
     "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
-    "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy",
+    "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy", "ptyhip_forward_adjoint_static",
 ]
 
 
@@ -102,6 +103,8 @@ def _lib():
         L.ptyhip_batch_bind.argtypes = [_vp, _i32] + [_vp] * 10
         L.ptyhip_batch_launch.argtypes = [_vp, _vp, _u32]
         L.ptyhip_batch_get_error.argtypes = [_vp, _vp, ctypes.POINTER(_u32)]
+        L.ptyhip_forward_adjoint_static.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Tune), _vp, _i32, _u32] + \
+            [_vp] * 12
         L.ptyhip_batch_destroy.argtypes = [_vp]
         L.ptyhip_batch_destroy.restype = None
         for name in EXPORTED:
@@ -420,3 +423,50 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def forward_adjoint_static(desc: Desc, obj, probe, positions, I_meas, weights=None,
+                           grads: Sequence[str] = ("obj", "probe"), tune: Optional[dict] = None,
+                           accumulate=False, out: Optional[dict] = None, I_pred=None, stream=None):
+    """``Plan.forward_adjoint`` without a plan (``ptyhip_forward_adjoint_static``): the
+    library allocates nothing; its buffers come from a fixed device array. ``desc`` is a
+    ``make_desc`` description. The output dict also holds ``flags`` (device uint32, the
+    call's error latch). Outputs missing from ``out`` are allocated here, by torch, before
+    the call."""
+    N, M, E = int(desc.frame), int(desc.n_modes), int(desc.n_eig)
+    K = int(positions.shape[0])
+    _need(obj, "obj", torch.complex64, (int(desc.n_slices), int(desc.obj_h), int(desc.obj_w)))
+    _need(probe, "probe", torch.complex64, (E, M, N, N))
+    _need(positions, "positions", torch.float32, (K, 2))
+    _need(I_meas, "I_meas", torch.float32, (K, N, N))
+    if weights is not None:
+        _need(weights, "weights", torch.float32, (K, E))
+    dev = obj.device
+    out = dict(out or {})
+    out.setdefault("loss", torch.zeros(1, dtype=torch.float64, device=dev))
+    out.setdefault("flags", torch.zeros(1, dtype=torch.int32, device=dev))
+    flags = 0
+    shapes = {"obj": ("g_obj", GRAD_OBJ, (int(desc.n_slices), int(desc.obj_h), int(desc.obj_w)), torch.complex64),
+              "probe": ("g_probe", GRAD_PROBE, (E, M, N, N), torch.complex64),
+              "pos": ("g_pos", GRAD_POS, (K, 2), torch.float32),
+              "weights": ("g_weights", GRAD_WEIGHTS, (K, E), torch.float32)}
+    for g in grads:
+        key, bit, shape, dt = shapes[g]
+        flags |= bit
+        if key not in out:
+            out[key] = torch.zeros(shape, dtype=dt, device=dev)
+    if accumulate:
+        flags |= ACCUMULATE
+    if I_pred is not None:
+        _need(I_pred, "I_pred", torch.float32, (K, N, N))
+        out["I_pred"] = I_pred
+    tu = None
+    if tune:
+        tu = ctypes.byref(Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)), int(tune.get("recompute", 0)),
+                               int(tune.get("plain_chunk", 0))))
+    st = _lib().ptyhip_forward_adjoint_static(
+        ctypes.byref(desc), tu, _stream(stream), K, flags, _ptr(obj), _ptr(probe), _ptr(weights), _ptr(positions),
+        _ptr(I_meas), _ptr(out["loss"]), _ptr(I_pred), _ptr(out.get("g_obj")), _ptr(out.get("g_probe")),
+        _ptr(out.get("g_pos")), _ptr(out.get("g_weights")), _ptr(out["flags"]))
+    _check(st, "ptyhip_forward_adjoint_static")
+    return out
