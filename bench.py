@@ -171,6 +171,11 @@ WORKLOADS = {
           "lambda z = 81.92 px^2, amplitude loss, gradients of all slices, probe and positions",
     "c5": "config 5 (mode-heavy): 413x535 object, 30 probe modes of 128x128, 6732 raster positions with "
           "sub-pixel offsets, amplitude loss, gradients of object, probe and positions",
+    "c6": "config 6 (the supplement's speed-benchmark shape): 961 positions of 128^2, 15 probe modes, 3 OPR "
+          "eigenprobes with per-position weights, 372x372 object, amplitude loss, gradients of object, "
+          "eigenprobes and weights",
+    "c6n512": "config 6 at 512^2 frames: 961 positions, 15 probe modes, 3 OPR eigenprobes, 1476x1476 object, "
+              "amplitude loss, gradients of object, eigenprobes and weights",
     "c4": "config 4: 32 independent datasets (64^2-512^2 frames, 1-4 modes, 200-5000 positions each, "
           "per-position probe amplitudes), one batched persistent launch captured in a hipGraph, amplitude loss, "
           "gradients of objects, probes, positions and weights",
@@ -184,6 +189,8 @@ def build_workload(name):
     if name == "c1m0":
         truth = W.make_config(1)
         truth = dataclasses.replace(truth, probe=truth.probe[:, :1].copy())
+    elif name == "c6n512":
+        truth = W.make_config(6, N=512)
     else:
         truth = W.make_config(int(name[1:]))
     return truth, W.perturb(truth, 21)
@@ -271,6 +278,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-step form")
     ap.add_argument("--no-autograd", action="store_true", help="skip the autograd form")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="positions per call (minibatch call shape); 0 = the whole workload in one call")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each distinct call from a captured hipGraph (plan graph cache)")
     ap.add_argument("--tune", default=None,
                     help="fixed implementation choice as JSON (skips the autotuner; used for profiling runs)")
     ap.add_argument("--retune", action="store_true", help="ignore the frozen tune cache and autotune again")
@@ -324,14 +335,33 @@ def main():
     if args.tune:
         tune, tune_src = json.loads(args.tune), "fixed"
     else:
-        tune, rep = autotune.tune_plan(shape, obj, probe, pos, I_meas, weights=wts, grads=grads, cache_path=cache,
+        Bt = min(args.batch, truth.K) if args.batch > 0 else truth.K
+        tune, rep = autotune.tune_plan(shape, obj, probe, pos[:Bt], I_meas[:Bt],
+                                       weights=None if wts is None else wts[:Bt], grads=grads, cache_path=cache,
                                        use_cache=not args.retune)
         tune_src = "cache" if rep.get("cached") else "autotuned"
-    plan = Plan.for_problem(start, tune=tune)
-    out = plan.forward_adjoint(obj, probe, pos, I_meas, weights=wts, grads=grads)
+    # call shape: the whole workload in one call, or minibatches of B positions (each call
+    # normalised by its own position count, as a minibatch reconstructor calls it); a step
+    # is one pass over every position either way
+    K_all = truth.K
+    B = min(args.batch, K_all) if args.batch > 0 else K_all
+    calls = []
+    for a in range(0, K_all, B):
+        b = min(a + B, K_all)
+        calls.append((pos[a:b], I_meas[a:b], None if wts is None else wts[a:b]))
+    plan = Plan.for_problem(start, max_positions=B, tune=tune)
+    if args.graphs:
+        plan.set_graphs(True)
+    outs = {}
+    for (p_, m_, w_) in calls:
+        n = int(p_.shape[0])
+        if n not in outs:
+            outs[n] = plan.forward_adjoint(obj, probe, p_, m_, weights=w_, grads=grads)
 
     def step(plain=False):
-        plan.forward_adjoint(obj, probe, pos, I_meas, weights=wts, grads=grads, out=out, plain=plain)
+        for (p_, m_, w_) in calls:
+            plan.forward_adjoint(obj, probe, p_, m_, weights=w_, grads=grads, out=outs[int(p_.shape[0])],
+                                 plain=plain)
 
     for _ in range(args.warmup):
         step()
@@ -383,7 +413,7 @@ def main():
     # the autograd form (torch.autograd.Function over the same plan): forward + backward
     # of the loss with respect to the same leaves, timed the same way as the per-call form
     autograd = None
-    if not args.no_autograd:
+    if not args.no_autograd and len(calls) == 1:
         from paper_2510_20929_amd import ptycho_loss
         leaves = {"obj": obj.clone().requires_grad_("obj" in grads),
                   "probe": probe.clone().requires_grad_("probe" in grads),
@@ -417,7 +447,8 @@ def main():
         "ms_per_step": ms_step,
         "config": {"workload": WORKLOADS[args.workload], "frame": start.N, "modes": start.M,
                    "eigenprobes": start.E, "slices": start.S, "positions": K, "object": [start.H, start.W],
-                   "loss": start.loss, "form": "fused persistent kernel"},
+                   "loss": start.loss, "form": "fused persistent kernel",
+                   "positions_per_call": B, "calls_per_step": len(calls), "graph_replay": bool(args.graphs)},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": kernel_name(plan, start, tune),

@@ -252,6 +252,18 @@ ptyhip_status ptyhip_normalize_gradients(ptyhip_plan plan, void* stream, int32_t
 ptyhip_status ptyhip_orthogonalize_modes(ptyhip_plan plan, void* stream, const float* probe, float* probe_out,
                                          double* powers);
 
+/* Graph replay of repeated calls (for launch-bound loops of small calls, such as
+ * minibatches visited epoch after epoch, Performance benchmarking). When enabled, the
+ * first ptyhip_forward / ptyhip_forward_adjoint[_ex] call with a given argument set (every
+ * pointer, K and the flags) captures its launch chain (fused kernel, object-gradient
+ * gather, reductions) into a hipGraph on a stream of the plan and launches it on `stream`;
+ * later calls with the same set replay that graph. The data behind the pointers may change
+ * between calls; the buffers must stay allocated while the plan caches graphs that use
+ * them (disabling the option, or destroying the plan, releases the graphs). Up to 4096
+ * argument sets are kept; beyond that the cache is emptied. With timing enabled, a
+ * replayed call is timed as one unit (its whole chain). Disabling synchronises the device. */
+ptyhip_status ptyhip_plan_set_graphs(ptyhip_plan plan, int32_t enable);
+
 /* Kernel timing: when enabled, every call records a pair of HIP events on its stream
  * immediately around its main kernel (the fused kernel, or the whole per-step chain).
  * ptyhip_plan_kernel_time waits for those events, returns the summed milliseconds and

@@ -46,6 +46,8 @@ static std::vector<float2> fresnel(int N, double lz) {
 }
 
 Plan::~Plan() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+  if (gstream) (void)hipStreamDestroy(gstream);
   for (void* p : allocs) (void)hipFree(p);
   for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
   for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
@@ -145,10 +147,11 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   const size_t win_budget = size_t(2) << 30;
   p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(maxK, 1)), win_budget / win)));
   if (p->whole_windows) p->fchunk = std::max(maxK, 1);
-  // large frames with several eigenprobes: the fused kernel stages each position's
-  // probe-wave gradients and a separate pass forms sum_k w_k,e gP_k for every eigenprobe
-  // (one write per pixel instead of E read-modify-writes); chunk bounded to 2 GiB
-  const bool stage = !p->on_chip && S == 1 && E > 1 && !p->whole_windows;
+  // several eigenprobes: the fused kernel stages each position's probe-wave gradients
+  // and a separate pass forms sum_k w_k,e gP_k for every eigenprobe (one write per pixel
+  // and mode instead of E read-modify-writes of the workgroup's accumulator frames);
+  // chunk bounded to 2 GiB
+  const bool stage = S == 1 && E > 1 && !p->whole_windows;
   if (stage) {
     const size_t per = size_t(M) * NN * sizeof(float2);
     p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(p->fchunk), win_budget / per)));
@@ -332,14 +335,17 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
     if (want_probe && !acc && launch_fill(g_probe, p->probe_elems * 2, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
     return PTYHIP_OK;
   }
+  // no more persistent workgroups than positions: an idle workgroup would still clear and
+  // hand in its probe-gradient accumulator
+  const int grid = std::max(1, std::min(p->grid, a.K));
   for (int k0 = 0; k0 < a.K; k0 += p->fchunk) {
     const int n = std::min(p->fchunk, a.K - k0);
     CallArgs c = chunk_args(a, k0, n, N, d.n_eig, d.n_modes);
     const bool staged = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
     c.gpstage = staged ? p->gpstage : nullptr;
     timing_begin(p, st);
-    hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, p->grid, st)
-                              : launch_fused_big(c, N, p->tune.variant, p->grid, st);
+    hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, grid, st)
+                              : launch_fused_big(c, N, p->tune.variant, grid, st);
     timing_end(p, st);
     if (e != hipSuccess) return PTYHIP_EHIP;
     if (want_obj) {
@@ -365,18 +371,77 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
   const bool staged_all = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
   if (want_probe && !staged_all) {
     hipError_t e = p->on_chip
-                       ? launch_probe_reduce_small(a, N, p->tune.variant, p->grid, reinterpret_cast<float2*>(g_probe),
+                       ? launch_probe_reduce_small(a, N, p->tune.variant, grid, reinterpret_cast<float2*>(g_probe),
                                                    acc ? 1 : 0, st)
-                       : launch_probe_reduce_big(a, N, p->grid, reinterpret_cast<float2*>(g_probe), acc ? 1 : 0, st);
+                       : launch_probe_reduce_big(a, N, grid, reinterpret_cast<float2*>(g_probe), acc ? 1 : 0, st);
     if (e != hipSuccess) return PTYHIP_EHIP;
   }
   return PTYHIP_OK;
 }
 
+static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
+                                             const float* probe, const float* weights, const float* positions,
+                                             const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                             float* g_probe, float* g_pos, float* g_weights, double* g_lz,
+                                             bool forward_only);
+
+constexpr size_t kMaxGraphs = 4096;
+
+// A call with the plan's graph replay on: the first call with a given argument set
+// (pointers, K, flags) is captured into a hipGraph on the plan's capture stream and
+// every call with that set replays it on `st`. Host-side checks run before the cache.
 ptyhip_status call_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
                                    const float* probe, const float* weights, const float* positions,
                                    const float* I_meas, double* loss, float* I_pred, float* g_obj, float* g_probe,
                                    float* g_pos, float* g_weights, double* g_lz, bool forward_only) {
+  if (p == nullptr || !p->use_graphs || K == 0)
+    return enqueue_forward_adjoint(p, st, K, flags, obj, probe, weights, positions, I_meas, loss, I_pred, g_obj,
+                                   g_probe, g_pos, g_weights, g_lz, forward_only);
+  const std::array<uintptr_t, 16> key = {
+      uintptr_t(K), uintptr_t(flags) | (forward_only ? (uintptr_t(1) << 40) : 0), uintptr_t(obj), uintptr_t(probe),
+      uintptr_t(weights), uintptr_t(positions), uintptr_t(I_meas), uintptr_t(loss), uintptr_t(I_pred),
+      uintptr_t(g_obj), uintptr_t(g_probe), uintptr_t(g_pos), uintptr_t(g_weights), uintptr_t(g_lz), 0, 0};
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    if (p->graphs.size() >= kMaxGraphs) {
+      if (hipStreamSynchronize(st) != hipSuccess) return PTYHIP_EHIP;
+      for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
+      p->graphs.clear();
+    }
+    // the capture only records the launches; validation errors return before any launch
+    const bool timing = p->timing;
+    p->timing = false;
+    if (hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      p->timing = timing;
+      return PTYHIP_EHIP;
+    }
+    ptyhip_status s = enqueue_forward_adjoint(p, p->gstream, K, flags, obj, probe, weights, positions, I_meas, loss,
+                                              I_pred, g_obj, g_probe, g_pos, g_weights, g_lz, forward_only);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    p->timing = timing;
+    if (s != PTYHIP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess || !g) return PTYHIP_EHIP;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess || !exec) return PTYHIP_EHIP;
+    it = p->graphs.emplace(key, exec).first;
+  }
+  timing_begin(p, st);
+  const hipError_t e = hipGraphLaunch(it->second, st);
+  timing_end(p, st);
+  return e == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
+}
+
+static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uint32_t flags, const float* obj,
+                                             const float* probe, const float* weights, const float* positions,
+                                             const float* I_meas, double* loss, float* I_pred, float* g_obj,
+                                             float* g_probe, float* g_pos, float* g_weights, double* g_lz,
+                                             bool forward_only) {
   if (p == nullptr) return PTYHIP_EINVAL;
   if (K < 0 || K > p->maxK) return PTYHIP_EBOUNDS;
   const ptyhip_desc& d = p->d;
@@ -664,6 +729,21 @@ ptyhip_status ptyhip_apply_AH(ptyhip_plan plan, void* stream, int32_t K, const f
     f.E = p->d.n_eig;
     if (launch_finalize(f, st) != hipSuccess) return PTYHIP_EHIP;
   }
+  return PTYHIP_OK;
+}
+
+ptyhip_status ptyhip_plan_set_graphs(ptyhip_plan plan, int32_t enable) {
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return PTYHIP_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return PTYHIP_EHIP;
+  if (enable && !p->gstream && hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking) != hipSuccess)
+    return PTYHIP_EHIP;
+  if (!enable && !p->graphs.empty()) {
+    if (hipDeviceSynchronize() != hipSuccess) return PTYHIP_EHIP;
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
+    p->graphs.clear();
+  }
+  p->use_graphs = enable != 0;
   return PTYHIP_OK;
 }
 

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../../include/ptyhip.h"
@@ -63,6 +65,11 @@ struct Plan {
   double* mode_gram = nullptr;  // [M][M][2]
   double* mode_vec = nullptr;   // [M][M][2]
   double* mode_pow = nullptr;   // [M]
+  // graph replay of repeated calls: the launch chain of a call (fused kernel, gather,
+  // reductions) captured once per distinct argument set and replayed afterwards
+  bool use_graphs = false;
+  hipStream_t gstream = nullptr;  // capture stream (capture is not allowed on the legacy default stream)
+  std::map<std::array<uintptr_t, 16>, hipGraphExec_t> graphs;
   // kernel timing (events recorded around the main kernel of each call)
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;

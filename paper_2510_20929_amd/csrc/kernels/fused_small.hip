@@ -52,7 +52,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   float2* pacc = scr + a.pacc_off;
   const BufFrame sbf(scr, uint32_t(a.scratch_stride * sizeof(float2)));
   const size_t HW = size_t(a.H) * a.W;
-  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, pacc);
+  if (adj && a.zero_acc && (a.want & WANT_PROBE) && !a.gpstage) zero_probe_acc<N, T>(a, pacc);
 
   // multiply by the slice transfer function (or its conjugate) in layout D
   auto apply_tf = [&](float2 (&v)[E], bool conj) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
           F::inverse(v, lds, tws, inv_n);
         }
       }
-      probe_gradients<N, T>(a, m, wk, v, sbf, int(a.pacc_off * sizeof(float2)), red, wacc);
+      probe_gradients<N, T>(a, k, m, wk, v, sbf, int(a.pacc_off * sizeof(float2)), red, wacc);
     }
     if constexpr (LZ) {
       const double tot = block_sum<T>(lz, red);

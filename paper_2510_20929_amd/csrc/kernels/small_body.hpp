@@ -170,18 +170,24 @@ __device__ __forceinline__ void zero_probe_acc(const CallArgs& a, float2* acc) {
 }
 
 // Probe-side gradients of one mode from the gradient gP of the incident probe wave
-// (layout A): accumulate w_e gP into the workgroup's accumulator frames ([E][M] frames
-// starting at byte offset acc_b of the scratch buffer `sb`), and the OPR weight-gradient
-// sums Re<gP, U_e,m>.
+// (layout A) of position k: accumulate w_e gP into the workgroup's accumulator frames
+// ([E][M] frames starting at byte offset acc_b of the scratch buffer `sb`), or, with
+// several eigenprobes (a.gpstage set), write gP once to the position's staging frame
+// (natural pixel order) for the separate eigenprobe reduction sum_k w_k,e gP_k; and the
+// OPR weight-gradient sums Re<gP, U_e,m>.
 // The accumulator is read CH elements at a time (all loads of a chunk in flight).
 template <int N, int T, int CH = Frame2D<N, T>::E>
-__device__ __forceinline__ void probe_gradients(const CallArgs& a, int m, const float* wk,
+__device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m, const float* wk,
                                                 const float2 (&gP)[Frame2D<N, T>::E], const BufFrame& sb, int acc_b,
                                                 double* red, double* wacc) {
   using C = SmallCtx<N, T>;
   static_assert(C::E % CH == 0, "chunk must divide the elements per thread");
   const int t = opaque_tid();
-  if (a.want & WANT_PROBE) {
+  if ((a.want & WANT_PROBE) && a.gpstage) {
+    float2* st = a.gpstage + (size_t(k) * a.M + m) * C::NN;
+#pragma unroll
+    for (int i = 0; i < C::E; ++i) st[C::a_pix(t, i)] = gP[i];
+  } else if (a.want & WANT_PROBE) {
     const int ne = wk ? a.E : 1;
     for (int e = 0; e < ne; ++e) {
       const int fb = acc_b + (e * a.M + m) * C::NN * 8;
@@ -338,7 +344,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
   constexpr int PSIS_B = (RV ? (GO_IN_REGS ? C::NN / 2 : C::NN / 2 + C::NN) : 2 * C::NN) * 8;
   const int pacc_b = int(a.pacc_off * sizeof(float2));
   const int fsx_b = pacc_b - C::NN * 8;  // FS: shifted window spectrum
-  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  if (adj && a.zero_acc && (a.want & WANT_PROBE) && !a.gpstage) zero_probe_acc<N, T>(a, scr + a.pacc_off);
   // FS: shift phase exp(2 pi i (ky fy + kx fx) / N) of element i (layout D) and the
   // signed frequencies 2 pi k / N
   auto shift_of = [&](const PosInfo& p, int t, int i, float& cy, float& cx) {
@@ -509,7 +515,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
           else pass(T0{}, T0{});
         }
       }
-      probe_gradients<N, T, (GO_IN_REGS ? 4 : E)>(a, m, wk, v, sb, pacc_b, red, wacc);
+      probe_gradients<N, T, (GO_IN_REGS ? 4 : E)>(a, k, m, wk, v, sb, pacc_b, red, wacc);
     }
 
     __syncthreads();
@@ -594,7 +600,7 @@ __device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N
   constexpr int GACC_B = C::NN * 8;
   constexpr int X_B = 2 * C::NN * 8;
   const int pacc_b = int(a.pacc_off * sizeof(float2));
-  if (adj && a.zero_acc && (a.want & WANT_PROBE)) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  if (adj && a.zero_acc && (a.want & WANT_PROBE) && !a.gpstage) zero_probe_acc<N, T>(a, scr + a.pacc_off);
 
   for (int k = wg; k < a.K; k += nwg) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
@@ -698,7 +704,7 @@ __device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N
           else pass(T0{}, T0{});
         }
       }
-      probe_gradients<N, T>(a, m, wk, v, sb, pacc_b, red, wacc);
+      probe_gradients<N, T>(a, k, m, wk, v, sb, pacc_b, red, wacc);
     }
     if (want_lz) {
       const double tot = block_sum<T>(lz, red);

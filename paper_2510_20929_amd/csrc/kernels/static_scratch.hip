@@ -125,7 +125,9 @@ extern "C" ptyhip_status ptyhip_forward_adjoint_static(const ptyhip_desc* desc, 
   // room for a chunk of up to 64 positions; then as many positions per chunk as fit
   const size_t keep = size_t(std::max(1, std::min(K, 64))) * per_pos;
   if (avail < keep + wg_bytes) return PTYHIP_ENOMEM;  // one workgroup and one position do not fit
-  const int want_grid = t.grid > 0 ? t.grid : cus;
+  // no more persistent workgroups than positions (an idle one would still clear and hand
+  // in its probe-gradient accumulator)
+  const int want_grid = std::max(1, std::min(t.grid > 0 ? t.grid : cus, K));
   const int grid = int(std::min<size_t>(size_t(want_grid), (avail - keep) / wg_bytes));
   const int C = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(K, 1)), (avail - size_t(grid) * wg_bytes) / per_pos)));
   size_t off = 0;

@@ -37,7 +37,7 @@ EXPORTED = [
     "ptyhip_plan_destroy", "ptyhip_plan_get_info", "ptyhip_forward", "ptyhip_forward_adjoint",
     "ptyhip_forward_adjoint_ex", "ptyhip_apply_A",
     "ptyhip_apply_AH", "ptyhip_illumination", "ptyhip_normalize_gradients",
-    "ptyhip_orthogonalize_modes", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
+    "ptyhip_orthogonalize_modes", "ptyhip_plan_set_graphs", "ptyhip_plan_set_timing", "ptyhip_plan_kernel_time", "ptyhip_get_error",
     "ptyhip_clear_error", "ptyhip_batch_create", "ptyhip_batch_bind",
     "ptyhip_batch_launch", "ptyhip_batch_get_error", "ptyhip_batch_destroy", "ptyhip_forward_adjoint_static",
 ]
@@ -94,6 +94,7 @@ def _lib():
         L.ptyhip_forward_adjoint.argtypes = [_vp, _vp, _i32, _u32] + [_vp] * 11
         L.ptyhip_apply_A.argtypes = [_vp, _vp, _i32] + [_vp] * 5
         L.ptyhip_apply_AH.argtypes = [_vp, _vp, _i32] + [_vp] * 7
+        L.ptyhip_plan_set_graphs.argtypes = [_vp, _i32]
         L.ptyhip_plan_set_timing.argtypes = [_vp, _i32]
         L.ptyhip_plan_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
         L.ptyhip_get_error.argtypes = [_vp, _vp, ctypes.POINTER(_u32)]
@@ -337,6 +338,10 @@ class Plan:
         st = _lib().ptyhip_orthogonalize_modes(self._h, _stream(stream), _ptr(probe), _ptr(out), _ptr(powers))
         _check(st, "ptyhip_orthogonalize_modes")
         return out, powers
+
+    def set_graphs(self, enable: bool = True):
+        """Replay repeated calls (same tensors, K and flags) from captured hipGraphs."""
+        _check(_lib().ptyhip_plan_set_graphs(self._h, 1 if enable else 0), "ptyhip_plan_set_graphs")
 
     def set_timing(self, enable: bool = True):
         _check(_lib().ptyhip_plan_set_timing(self._h, 1 if enable else 0), "ptyhip_plan_set_timing")

@@ -279,11 +279,44 @@ def _config5(rng, H: int, W: int, K: int, M: int) -> Problem:
                    "amplitude", grads=("obj", "probe", "pos"))
 
 
+def _config6(rng, N: int, K: int) -> Problem:
+    """The supplement's speed-benchmark shape: 961 diffraction patterns, 15 incoherent probe
+    modes and 3 OPR eigenprobes (the primary one included), frames of 128^2 or 512^2,
+    amplitude loss, position correction disabled (object, eigenprobe and weight gradients).
+    The paper states no object, scan or probe for it: a 31 x 31 raster at N / 16 px steps
+    with sub-pixel offsets over an object of scan extent + N + 4; eigenprobe 0 holds 15
+    orthonormal Hermite-Gauss modes (waist N / 8, powers exp(-j / 4)); eigenprobes 1 and 2
+    are the same modes times smooth random fields (the slow drift OPR models); weights
+    N(1, 0.1) for the primary eigenprobe and N(0, 0.05) for the others."""
+    M, E = 15, 3
+    side = 31
+    step = N / 16.0
+    H = int(math.ceil((side - 1) * step)) + N + 4
+    obj = random_object(rng, H, H)[None]
+    powers = np.exp(-np.arange(M) / 4.0)
+    powers = powers / powers.sum()
+    modes = _hg_modes(N, _mode_orders(M), N / 8.0, powers, N / 4.0)
+    eig = [modes]
+    for _ in range(E - 1):
+        field = smooth_field((N, N), N / 16.0, rng) + 1j * smooth_field((N, N), N / 16.0, rng)
+        eig.append(modes * (0.5 * field)[None])
+    U = np.stack(eig)
+    pos = raster(side, side, step, 1.0, 1.0) + rng.uniform(0.0, 1.0, size=(side * side, 2))
+    pos = pos[:K]
+    w = np.empty((pos.shape[0], E), dtype=np.float64)
+    w[:, 0] = rng.normal(1.0, 0.1, size=pos.shape[0])
+    w[:, 1:] = rng.normal(0.0, 0.05, size=(pos.shape[0], E - 1))
+    U = U * _photon_scale(U[0], obj, PHOTONS_PER_FRAME)
+    return Problem(f"c6n{N}", obj, U.astype(np.complex64), pos.astype(np.float32), w.astype(np.float32),
+                   "amplitude", grads=("obj", "probe", "weights"))
+
+
 def make_config(c: int, *, H: Optional[int] = None, K: Optional[int] = None,
-                S: Optional[int] = None, W: Optional[int] = None, M: Optional[int] = None) -> Problem:
-    """Truth problem for config ``c`` (0-3, 5). H, K, S shrink it for tests while keeping
+                S: Optional[int] = None, W: Optional[int] = None, M: Optional[int] = None,
+                N: Optional[int] = None) -> Problem:
+    """Truth problem for config ``c`` (0-3, 5, 6). H, K, S shrink it for tests while keeping
     the frame size, the mode/eigenprobe structure and the scan pattern (config 5 also
-    takes W and the mode count M)."""
+    takes W and the mode count M; config 6 takes the frame size N, 128 or 512, and K)."""
     rng = np.random.default_rng(SEED_BASE + c)
     if c == 0:
         return _config0(rng, H or 256, K)
@@ -295,6 +328,8 @@ def make_config(c: int, *, H: Optional[int] = None, K: Optional[int] = None,
         return _config3(rng, S or 8, H or 2048, K or 5000)
     if c == 5:
         return _config5(rng, H or 413, W or 535, K or 6732, M or 30)
+    if c == 6:
+        return _config6(rng, N or 128, K or 961)
     raise ValueError(f"unknown config {c}")
 
 
