@@ -232,17 +232,27 @@ def run_batched(args, dev, torch, t):
     truths = W.make_batched_config()
     starts = [W.perturb(p, 3) for p in truths]
     grads = ("obj", "probe", "pos", "weights")
-    b = Batch(starts)
-    outs = []
-    for i, (tr, st) in enumerate(zip(truths, starts)):
+    tensors = []
+    for tr, st in zip(truths, starts):
         I = measured_intensities(tr, dev, torch, t, Plan)
-        outs.append(b.bind(i, t(st.obj), t(st.probe), t(st.positions), I, weights=t(st.weights)))
+        tensors.append((t(st.obj), t(st.probe), t(st.positions), I, t(st.weights)))
+    # schedule by the autotuner (parity-gated against one call per dataset, cached)
+    from paper_2510_20929_amd import autotune
+    if args.tune:
+        choice, src = json.loads(args.tune), "fixed"
+    else:
+        cache = os.environ.get("PTYHIP_TUNE_CACHE") or autotune.DEFAULT_CACHE
+        choice, rep = autotune.tune_batch(starts, tensors, grads=grads, cache_path=cache, use_cache=not args.retune)
+        src = "cache" if rep.get("cached") else "autotuned"
+    per_call_choice = bool(choice.get("per_call"))
+    b = Batch(starts, tune=None if per_call_choice else choice)
+    outs = [b.bind(i, *ts[:4], weights=ts[4]) for i, ts in enumerate(tensors)]
     for _ in range(args.warmup):
-        b.launch(grads)
+        b.launch(grads, per_call=per_call_choice)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        b.launch(grads)
+        b.launch(grads, per_call=per_call_choice)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     K = sum(p.K for p in truths)
@@ -263,8 +273,13 @@ def run_batched(args, dev, torch, t):
             "hbm": {"alg_GBs": byts / (ms * 1e-3) / 1e9, "frac_of_peak": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "per_call": {"value": K / (per_call_ms * 1e-3), "ms_per_step": per_call_ms},
             "batched_vs_per_call": per_call_ms / ms, "error_flags": b.get_error(),
+            "tune": choice, "tune_source": src,
             "config": {"datasets": len(truths), "positions": K,
-                       "frames": sorted({p.N for p in truths}), "form": "batched persistent kernel, hipGraph replay"}}
+                       "frames": sorted({p.N for p in truths}),
+                       "form": ("one call per dataset (the autotuner's choice)" if per_call_choice else
+                                "batched persistent launches per frame-size class, " +
+                                ("concurrent graph branches" if choice.get("variant") == 1 else "one after the other")
+                                + ", hipGraph replay")}}
 
 
 def main():

@@ -310,7 +310,11 @@ ptyhip_status ptyhip_forward_adjoint_static(const ptyhip_desc* desc, const ptyhi
 
 /* Many independent reconstructions of uneven frame sizes in one persistent launch per
  * frame size (64^2, 128^2, 256^2, 512^2), captured once into a hipGraph and replayed (Sec. 2.1: scan points and modes are
- * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. */
+ * processed together). descs[i] / K[i] describe dataset i; tune may be NULL. For a batch,
+ * tune->grid is the workgroup total of a launch (0: one per CU) and tune->variant the
+ * schedule of the frame-size classes: 0 = one after the other, each launch on the whole
+ * GPU; 1 = concurrently, as parallel branches of the graph whose launches split the
+ * total in proportion to their classes' work (other values are PTYHIP_EINVAL). */
 ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, int32_t n, const ptyhip_tune* tune,
                                   ptyhip_batch* out);
 /* Bind dataset i's device arrays (same meaning as in ptyhip_forward_adjoint). Rebinding

@@ -180,10 +180,26 @@ def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("
     return best[0], {"key": key, "cached": False, "candidates": results}
 
 
-def tune_batch(problems, tensors, grads=("obj", "probe", "pos"), reps: int = 3, log=None):
-    """Pick the total workgroup count of the batched launch (or one call per dataset).
-    ``tensors[i]`` = (obj, probe, positions, I_meas, weights) on the device. Every
-    candidate must reproduce the per-call results of each dataset. Returns (choice, report)."""
+def batch_key(problems, grads) -> str:
+    """Cache key of a batch: architecture, sources, every dataset's shape and the gradients."""
+    h = hashlib.sha256()
+    for p in problems:
+        h.update(f"{p.N},{p.M},{p.E},{p.S},{p.H},{p.W},{p.K},{p.loss};".encode())
+    return f"{_arch()}|src{source_hash()}|batch{len(problems)}|{h.hexdigest()[:12]}|{'+'.join(sorted(grads))}"
+
+
+def tune_batch(problems, tensors, grads=("obj", "probe", "pos"), reps: int = 3, log=None,
+               cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True):
+    """Pick the batched schedule: the workgroup total of a launch, the frame-size classes
+    one after the other or concurrently (graph branches sharing the CUs by work), or one
+    call per dataset. ``tensors[i]`` = (obj, probe, positions, I_meas, weights) on the
+    device. Every candidate must reproduce the per-call results of each dataset. The
+    choice is cached under ``batch_key``. Returns (choice, report)."""
+    key = batch_key(problems, grads)
+    if cache_path and use_cache:
+        cache = load_cache(cache_path)
+        if key in cache:
+            return cache[key]["tune"], {"key": key, "cached": True}
     cus = _cus()
     ref_b = Batch(problems)
     refs = [ref_b.bind(i, *t[:4], weights=t[4]) for i, t in enumerate(tensors)]
@@ -192,25 +208,33 @@ def tune_batch(problems, tensors, grads=("obj", "probe", "pos"), reps: int = 3, 
     ref = [{k: v.clone() for k, v in r.items()} for r in refs]
     results = []
     best = None
-    for total in (cus, 2 * cus, 4 * cus):
-        b = Batch(problems, tune={"grid": total})
-        outs = [b.bind(i, *t[:4], weights=t[4]) for i, t in enumerate(tensors)]
-        b.launch(grads)
-        torch.cuda.synchronize()
-        bad = None
-        for i, o in enumerate(outs):
-            bad = bad or _agrees(o, ref[i], grads)
-        if bad:
-            results.append({"grid": total, "parity": bad})
-            continue
-        ms = _time(lambda: b.launch(grads), reps)
-        results.append({"grid": total, "ms": ms})
-        if log:
-            log(f"batch grid {total}: {ms:.3f} ms")
-        if best is None or ms < best[1]:
-            best = ({"grid": total}, ms)
+    for variant in (0, 1):
+        for total in (cus, 2 * cus, 4 * cus):
+            cand = {"variant": variant, "grid": total}
+            b = Batch(problems, tune=cand)
+            outs = [b.bind(i, *t[:4], weights=t[4]) for i, t in enumerate(tensors)]
+            b.launch(grads)
+            torch.cuda.synchronize()
+            bad = None
+            for i, o in enumerate(outs):
+                bad = bad or _agrees(o, ref[i], grads)
+            if bad:
+                results.append({"tune": cand, "parity": bad})
+                continue
+            ms = _time(lambda: b.launch(grads), reps)
+            results.append({"tune": cand, "ms": ms})
+            if log:
+                log(f"batch {cand}: {ms:.3f} ms")
+            if best is None or ms < best[1]:
+                best = (cand, ms)
+            del b, outs
     ms = _time(lambda: ref_b.launch(grads, per_call=True), reps)
-    results.append({"per_call": True, "ms": ms})
+    results.append({"tune": {"per_call": True}, "ms": ms})
     if best is None or ms < best[1]:
         best = ({"per_call": True}, ms)
-    return best[0], {"candidates": results}
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache[key] = {"tune": best[0], "ms": best[1], "when": time.strftime("%Y-%m-%d %H:%M:%S"),
+                      "candidates": results}
+        save_cache(cache, cache_path)
+    return best[0], {"key": key, "cached": False, "candidates": results}

@@ -43,8 +43,19 @@ struct ptyhip_batch_s {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;  // capture stream (capture is not allowed on the legacy default stream)
   uint32_t graph_flags = 0xffffffffu;
+  // concurrent classes: each class's launch and follow-up reductions on a branch of its own,
+  // the classes sharing the CUs in proportion to their work
+  bool concurrent = false;
+  hipStream_t side[BATCH_CLASSES] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[BATCH_CLASSES] = {};
   ~ptyhip_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipStream_t s : side)
+      if (s) (void)hipStreamDestroy(s);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
     if (cap) (void)hipStreamDestroy(cap);
     if (graph) (void)hipGraphDestroy(graph);
     if (dev_tab) (void)hipFree(dev_tab);
@@ -60,6 +71,7 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
   if (!out) return PTYHIP_EINVAL;
   *out = nullptr;
   if (!descs || !K || n < 1 || n > 1024) return PTYHIP_EINVAL;
+  if (tune && (tune->variant < 0 || tune->variant > 1 || tune->grid < 0)) return PTYHIP_EINVAL;
   for (int i = 0; i < n; ++i) {
     ptyhip_status s = validate_desc(&descs[i]);
     if (s != PTYHIP_OK) return s;
@@ -89,9 +101,17 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
   }
   // per frame-size class: one workgroup per CU (a tuned total if given), one workgroup per
   // dataset at least, the rest by largest remainder in proportion to the work; inside a
-  // class the most expensive datasets take the first workgroups
+  // class the most expensive datasets take the first workgroups. Concurrent classes
+  // (tune variant 1) split that total among the classes in proportion to their work.
+  b->concurrent = tune && tune->variant == 1;
   b->n_wg.assign(n, 1);
   b->first_wg.assign(n, 0);
+  const int grid_total = (tune && tune->grid > 0) ? int(tune->grid) : prop.multiProcessorCount;
+  double cls_cost[BATCH_CLASSES] = {}, all_cost = 0.0;
+  for (int i = 0; i < n; ++i) {
+    cls_cost[batch_class(descs[i].frame)] += cost[i];
+    all_cost += cost[i];
+  }
   for (int c = 0; c < BATCH_CLASSES; ++c) {
     std::vector<int> members;
     for (int i = 0; i < n; ++i)
@@ -99,7 +119,8 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     const int nc = int(members.size());
     b->cls_count[c] = nc;
     if (nc == 0) continue;
-    const int total = std::max(nc, (tune && tune->grid > 0) ? int(tune->grid) : prop.multiProcessorCount);
+    const int share = b->concurrent ? int(std::lround(double(grid_total) * cls_cost[c] / all_cost)) : grid_total;
+    const int total = std::max(nc, share);
     b->cls_wg[c] = total;
     double tot = 0.0;
     for (int i : members) tot += cost[i];
@@ -161,6 +182,16 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return PTYHIP_EHIP;
+  }
+  if (b->concurrent) {
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int c = 0; c < BATCH_CLASSES && ok; ++c)
+      ok = hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&b->join[c], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      delete b;
+      return PTYHIP_EHIP;
+    }
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&b->staging), sizeof(BatchEntry) * n, hipHostMallocDefault) !=
           hipSuccess ||
@@ -275,7 +306,22 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
     b->graph = nullptr;
     // capture records the launches without running them; the graph then runs on `st`
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PTYHIP_EHIP;
-    hipError_t e = launch_batched(b->dev_tab, sorted.data(), b->n, b->cls_first, b->cls_count, b->cls_wg, b->cap);
+    hipError_t e = hipSuccess;
+    if (b->concurrent) {
+      // fork: every class's branch waits for the capture stream, then runs on its own stream;
+      // join: the capture stream waits for every branch
+      e = hipEventRecord(b->fork, b->cap);
+      for (int c = 0; c < BATCH_CLASSES && e == hipSuccess; ++c) {
+        if (b->cls_count[c] == 0) continue;
+        e = hipStreamWaitEvent(b->side[c], b->fork, 0);
+        if (e == hipSuccess)
+          e = launch_batched_class(b->dev_tab, sorted.data(), c, b->cls_first, b->cls_count, b->cls_wg, b->side[c]);
+        if (e == hipSuccess) e = hipEventRecord(b->join[c], b->side[c]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[c], 0);
+      }
+    } else {
+      e = launch_batched(b->dev_tab, sorted.data(), b->n, b->cls_first, b->cls_count, b->cls_wg, b->cap);
+    }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) return PTYHIP_EHIP;

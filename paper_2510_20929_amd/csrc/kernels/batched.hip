@@ -102,25 +102,25 @@ __global__ __launch_bounds__(1024) void batch_finalize_kernel(const BatchEntry* 
     for (int i = threadIdx.x; i < a.E * a.K; i += 1024) tab[d].g_w[i] = float(a.w_part[i]);
 }
 
-hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
-                          const int* cls_count, const int* cls_wg, hipStream_t st) {
-  for (int c = 0; c < BATCH_CLASSES; ++c) {
-    if (cls_count[c] == 0) continue;
-    const BatchEntry* t = dev_tab + cls_first[c];
-    const dim3 grid{unsigned(cls_wg[c])};
-    switch (c) {
-      case 0: hipLaunchKernelGGL(batched_64_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
-      case 1: hipLaunchKernelGGL(batched_128_kernel, grid, dim3(BT128), 0, st, t, cls_count[c]); break;
-      case 2: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
-      default: hipLaunchKernelGGL((batched_big_kernel<512, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
-    }
+// One frame-size class: its persistent launch, then the gather, probe reduction and final
+// reductions of its datasets (table entries [cls_first[c], cls_first[c] + cls_count[c])).
+hipError_t launch_batched_class(const BatchEntry* dev_tab, const BatchEntry* host_tab, int c, const int* cls_first,
+                                const int* cls_count, const int* cls_wg, hipStream_t st) {
+  if (cls_count[c] == 0) return hipSuccess;
+  const BatchEntry* t = dev_tab + cls_first[c];
+  const dim3 grid{unsigned(cls_wg[c])};
+  switch (c) {
+    case 0: hipLaunchKernelGGL(batched_64_kernel, grid, dim3(BT), 0, st, t, cls_count[c]); break;
+    case 1: hipLaunchKernelGGL(batched_128_kernel, grid, dim3(BT128), 0, st, t, cls_count[c]); break;
+    case 2: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
+    default: hipLaunchKernelGGL((batched_big_kernel<512, 1024>), grid, dim3(1024), 0, st, t, cls_count[c]); break;
   }
-  for (int d = 0; d < n; ++d) {
+  for (int d = cls_first[c]; d < cls_first[c] + cls_count[c]; ++d) {
     const BatchEntry& e = host_tab[d];
     if (e.a.mode != MODE_FWD_ADJ) continue;
     if (e.g.gobj) {
-      dim3 grid(unsigned((e.g.W + GT - 1) / GT), unsigned((e.g.H + GT - 1) / GT), unsigned(e.g.S));
-      hipLaunchKernelGGL(batch_gather_kernel, grid, dim3(256), 0, st, dev_tab, d);
+      dim3 g(unsigned((e.g.W + GT - 1) / GT), unsigned((e.g.H + GT - 1) / GT), unsigned(e.g.S));
+      hipLaunchKernelGGL(batch_gather_kernel, g, dim3(256), 0, st, dev_tab, d);
     }
     if (e.g_probe) {
       const size_t nel = size_t(e.a.E) * e.a.M * e.N * e.N;
@@ -135,8 +135,19 @@ hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab,
       }
     }
   }
-  for (int d = 0; d < n; ++d) hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, st, dev_tab, d);
+  for (int d = cls_first[c]; d < cls_first[c] + cls_count[c]; ++d)
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(1), dim3(1024), 0, st, dev_tab, d);
   return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
+                          const int* cls_count, const int* cls_wg, hipStream_t st) {
+  (void)n;
+  for (int c = 0; c < BATCH_CLASSES; ++c) {
+    const hipError_t e = launch_batched_class(dev_tab, host_tab, c, cls_first, cls_count, cls_wg, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ptyhip

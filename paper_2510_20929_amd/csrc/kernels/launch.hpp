@@ -116,5 +116,7 @@ int batch_class(int N);
 int batch_variant(int N);
 hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
                           const int* cls_count, const int* cls_wg, hipStream_t st);
+hipError_t launch_batched_class(const BatchEntry* dev_tab, const BatchEntry* host_tab, int c, const int* cls_first,
+                                const int* cls_count, const int* cls_wg, hipStream_t st);
 
 }  // namespace ptyhip

@@ -112,3 +112,26 @@ def test_batched_small_grid_vs_oracle(batch_case):
     for i, (p, I) in enumerate(zip(starts, meas)):
         ref = oracle.forward_adjoint(p.obj, p.probe, p.positions, I, weights=p.weights, loss=p.loss, grads=GRADS)
         compare(_np(outs[i]), ref, GRADS, tag=f"batched grid=8 {p.name} N={p.N} M={p.M} K={p.K}")
+
+
+@pytest.mark.parametrize("tune", [{"variant": 1}, {"variant": 1, "grid": 24}], ids=["concurrent", "concurrent-24"])
+def test_batched_concurrent_classes_vs_oracle(batch_case, tune):
+    """The frame-size classes as concurrent graph branches (launches sharing the CUs by
+    work), replayed twice: both replays against the oracle and bitwise equal."""
+    torch = torch_cuda()
+    from paper_2510_20929_amd import Batch
+    starts, meas = batch_case
+    b = Batch(starts, tune=tune)
+    outs = [b.bind(i, *_tensors(p, I)[:4], weights=_tensors(p, I)[4]) for i, (p, I) in enumerate(zip(starts, meas))]
+    b.launch(GRADS)
+    torch.cuda.synchronize()
+    first = [_np(o) for o in outs]
+    b.launch(GRADS)
+    torch.cuda.synchronize()
+    assert b.get_error() == 0
+    for i, (p, I) in enumerate(zip(starts, meas)):
+        again = _np(outs[i])
+        for k in first[i]:
+            assert np.array_equal(np.asarray(first[i][k]), np.asarray(again[k])), k
+        ref = oracle.forward_adjoint(p.obj, p.probe, p.positions, I, weights=p.weights, loss=p.loss, grads=GRADS)
+        compare(first[i], ref, GRADS, tag=f"batched {tune} {p.name} N={p.N} M={p.M} K={p.K}")
