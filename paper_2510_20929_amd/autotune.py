@@ -79,7 +79,10 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE) -> None:
     os.replace(tmp, path)
 
 
-def plan_candidates(N: int, M: int, S: int) -> List[dict]:
+def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True) -> List[dict]:
+    """Thread layout x far-field store/recompute x persistent grid; with few positions per
+    call and several modes (K below two workgroups per CU), also the mode-split form with
+    enough groups to give every CU one or two (position, group) items."""
     cus = _cus()
     out = []
     variants = [0, 1, 2, 3, 4] if N in (64, 128) else [0, 1]
@@ -89,6 +92,13 @@ def plan_candidates(N: int, M: int, S: int) -> List[dict]:
         for r in recomputes:
             for g in grids:
                 out.append({"variant": v, "recompute": r, "grid": g})
+    if split_ok and N <= 128 and S == 1 and M > 1 and 0 < K < 2 * cus:
+        groups = sorted({min(M, -(-c * cus // K)) for c in (1, 2)})
+        for G in groups:
+            if G < 2:
+                continue
+            for v in ([0, 4] if N in (64, 128) else [0]):
+                out.append({"variant": v, "recompute": 0, "grid": 0, "mode_groups": G})
     return out
 
 
@@ -154,7 +164,8 @@ def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("
     del ref_plan
     results = []
     best = None
-    for cand in plan_candidates(shape["N"], shape["M"], shape["S"]):
+    split_ok = shape.get("det_lambda_z") is None and shape.get("subpixel", "bilinear") == "bilinear"
+    for cand in plan_candidates(shape["N"], shape["M"], shape["S"], K, split_ok):
         plan = make(cand)
         out = plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads)
         torch.cuda.synchronize()

@@ -20,6 +20,7 @@ SOURCES = [
     "kernels/plain.hip",
     "kernels/fused_small.hip",
     "kernels/fused_small_fs.hip",
+    "kernels/fused_split.hip",
     "kernels/fused_big.hip",
     "kernels/finalize.hip",
     "kernels/gather.hip",

@@ -107,10 +107,19 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   }
   if ((st = dalloc(p, &p->flags, 1)) != PTYHIP_OK) return st;
   if (hipMemset(p->flags, 0, sizeof(uint32_t)) != hipSuccess) return PTYHIP_EHIP;
+  // mode-split form: at most mode_groups groups of ceil(M / groups) modes, none empty
+  if (p->tune.mode_groups > 1 && M > 1) {
+    p->group_modes = (M + std::min(p->tune.mode_groups, M) - 1) / std::min(p->tune.mode_groups, M);
+    p->groups = (M + p->group_modes - 1) / p->group_modes;
+  } else {
+    p->groups = 1;
+    p->group_modes = M;
+  }
+  const int G = p->groups;
   const size_t kk = size_t(std::max(maxK, 1));
   if ((st = dalloc(p, &p->loss_part, kk)) != PTYHIP_OK) return st;
-  if ((st = dalloc(p, &p->pos_part, kk * 2)) != PTYHIP_OK) return st;
-  if ((st = dalloc(p, &p->w_part, kk * E)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->pos_part, kk * 2 * G)) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->w_part, kk * E * G)) != PTYHIP_OK) return st;
   // per-position partials of dL/d(lambda z): the detector distance of the near field or
   // the slice spacing of a multislice model
   if ((d.propagation == PTYHIP_PROP_NEAR || S > 1) && (st = dalloc(p, &p->lz_part, kk)) != PTYHIP_OK) return st;
@@ -142,29 +151,36 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
     if ((st = dalloc(p, &p->scratch, p->scratch_stride * size_t(grid))) != PTYHIP_OK) return st;
     p->scratch_bytes = p->scratch_stride * size_t(grid) * sizeof(float2);
   }
-  // per-position window gradients of the fused form, chunked to a bounded footprint
-  const size_t win = size_t(S) * (N + 1) * (N + 1) * sizeof(float2);
+  // per-position window gradients of the fused form (one per mode group), chunked to a
+  // bounded footprint; the mode-split form also holds partial intensities and dl/dI
+  const size_t win = size_t(S) * (N + 1) * (N + 1) * sizeof(float2) * G +
+                     (G > 1 ? NN * sizeof(float) * (G + 1) + sizeof(int) : 0);
   const size_t win_budget = size_t(2) << 30;
   p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(std::max(maxK, 1)), win_budget / win)));
   if (p->whole_windows) p->fchunk = std::max(maxK, 1);
-  // several eigenprobes: the fused kernel stages each position's probe-wave gradients
-  // and a separate pass forms sum_k w_k,e gP_k for every eigenprobe (one write per pixel
-  // and mode instead of E read-modify-writes of the workgroup's accumulator frames);
-  // chunk bounded to 2 GiB
-  const bool stage = S == 1 && E > 1 && !p->whole_windows;
+  // several eigenprobes (and every mode-split plan): the fused kernel stages each
+  // position's probe-wave gradients and a separate pass forms sum_k w_k,e gP_k for every
+  // eigenprobe (one write per pixel and mode instead of E read-modify-writes of the
+  // workgroup's accumulator frames); chunk bounded to 2 GiB
+  const bool stage = S == 1 && (E > 1 || G > 1) && !p->whole_windows;
   if (stage) {
     const size_t per = size_t(M) * NN * sizeof(float2);
     p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(p->fchunk), win_budget / per)));
     const size_t part1 = size_t(E) * M * NN * sizeof(float2);
     p->eig_splits = int(std::max<size_t>(1, std::min<size_t>(8, (size_t(256) << 20) / part1)));
   }
-  if ((st = dalloc(p, &p->gwin, size_t(p->fchunk) * S * (N + 1) * (N + 1))) != PTYHIP_OK) return st;
-  if ((st = dalloc(p, &p->wvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->gwin, size_t(p->fchunk) * G * S * (N + 1) * (N + 1))) != PTYHIP_OK) return st;
+  if ((st = dalloc(p, &p->wvalid, size_t(p->fchunk) * G)) != PTYHIP_OK) return st;
+  if (G > 1) {
+    if ((st = dalloc(p, &p->ipart, size_t(p->fchunk) * G * NN)) != PTYHIP_OK) return st;
+    if ((st = dalloc(p, &p->cfr, size_t(p->fchunk) * NN)) != PTYHIP_OK) return st;
+    if ((st = dalloc(p, &p->kvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
+  }
   if (stage) {
     if ((st = dalloc(p, &p->gpstage, size_t(p->fchunk) * M * NN)) != PTYHIP_OK) return st;
     if ((st = dalloc(p, &p->eig_part, size_t(p->eig_splits) * E * M * NN)) != PTYHIP_OK) return st;
   }
-  p->window_bytes = size_t(p->fchunk) * win;
+  p->window_bytes = size_t(p->fchunk) * S * (N + 1) * (N + 1) * sizeof(float2) * G;
 
   // per-step path buffers, chunked to a bounded footprint
   const size_t per_pos = NN * sizeof(float2) * (size_t(S) * 2 + size_t(M) * 2 + (S > 1 ? size_t(S) * M : 0)) +
@@ -335,6 +351,51 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
     if (want_probe && !acc && launch_fill(g_probe, p->probe_elems * 2, 0.f, st) != hipSuccess) return PTYHIP_EHIP;
     return PTYHIP_OK;
   }
+  if (p->groups > 1 && (a.mode == MODE_FWD_ADJ || a.mode == MODE_FORWARD)) {
+    // mode-split form: three launches per chunk, one window per (position, group), staged
+    // probe-wave gradients, per-item position and weight partials
+    const int G = p->groups;
+    for (int k0 = 0; k0 < a.K; k0 += p->fchunk) {
+      const int n = std::min(p->fchunk, a.K - k0);
+      CallArgs c = chunk_args(a, k0, n, N, d.n_eig, d.n_modes);
+      c.pos_part = a.pos_part ? a.pos_part + size_t(2) * G * k0 : nullptr;
+      c.w_part = a.w_part ? a.w_part + size_t(d.n_eig) * G * k0 : nullptr;
+      c.groups = G;
+      c.group_modes = p->group_modes;
+      c.ipart = p->ipart;
+      c.cfr = a.mode == MODE_FWD_ADJ ? p->cfr : nullptr;
+      c.kvalid = p->kvalid;
+      c.gpstage = (want_probe && a.mode == MODE_FWD_ADJ) ? p->gpstage : nullptr;
+      c.gwin = want_obj ? p->gwin : nullptr;
+      c.wvalid = p->wvalid;
+      timing_begin(p, st);
+      hipError_t e = launch_fused_split(c, N, p->tune.variant, p->grid, st);
+      timing_end(p, st);
+      if (e != hipSuccess) return PTYHIP_EHIP;
+      if (a.mode != MODE_FWD_ADJ) continue;
+      const bool add = acc || k0 > 0;
+      if (want_obj) {
+        GatherArgs g{};
+        g.gwin = p->gwin;
+        g.wvalid = p->wvalid;
+        g.pos = c.pos;
+        g.gobj = reinterpret_cast<float2*>(g_obj);
+        g.K = n * G;
+        g.S = 1;
+        g.N = N;
+        g.H = d.obj_h;
+        g.W = d.obj_w;
+        g.accumulate = add ? 1 : 0;
+        g.rep = G;
+        if (launch_window_gather(g, st) != hipSuccess) return PTYHIP_EHIP;
+      }
+      if (want_probe &&
+          launch_eig_stage_reduce(p->gpstage, c.weights, p->kvalid, n, d.n_eig, d.n_modes, N, p->eig_splits,
+                                  p->eig_part, reinterpret_cast<float2*>(g_probe), add ? 1 : 0, st) != hipSuccess)
+        return PTYHIP_EHIP;
+    }
+    return PTYHIP_OK;
+  }
   // no more persistent workgroups than positions: an idle workgroup would still clear and
   // hand in its probe-gradient accumulator
   const int grid = std::max(1, std::min(p->grid, a.K));
@@ -349,7 +410,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
     timing_end(p, st);
     if (e != hipSuccess) return PTYHIP_EHIP;
     if (want_obj) {
-      GatherArgs g;
+      GatherArgs g{};
       g.gwin = p->gwin;
       g.wvalid = p->wvalid;
       g.pos = c.pos;
@@ -494,6 +555,7 @@ static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uin
   f.K = K;
   f.E = d.n_eig;
   f.accumulate = acc ? 1 : 0;
+  f.rep = (fused && p->groups > 1) ? p->groups : 1;
   return launch_finalize(f, st) == hipSuccess ? PTYHIP_OK : PTYHIP_EHIP;
 }
 
@@ -528,8 +590,12 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
   if (tune && (tune->variant < 0 || tune->variant > (desc->frame <= 128 ? 4 : 1) || tune->grid < 0 ||
-               tune->plain_chunk < 0 || tune->recompute < 0))
+               tune->plain_chunk < 0 || tune->recompute < 0 || tune->mode_groups < 0))
     return PTYHIP_EINVAL;
+  if (tune && tune->mode_groups > 1 &&
+      (desc->frame > 128 || desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||
+       desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR))
+    return PTYHIP_EUNSUPPORTED;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return PTYHIP_ENOMEM;
   s = plan_init(p, *desc, max_positions, tune);

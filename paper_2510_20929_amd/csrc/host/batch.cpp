@@ -158,6 +158,7 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
     b->plans[i] = p;
     ptyhip_tune t{};
     if (tune) t = *tune;
+    t.mode_groups = 0;  // a batch runs whole positions per workgroup
     t.grid = std::max(b->n_wg[i], prop.multiProcessorCount);
     // the body each class's launch runs: 128^2 the register-resident patch layout with
     // recomputed far fields (several modes), the others the default layout

@@ -48,6 +48,13 @@ struct Plan {
   bool whole_windows = false;  // window buffer for every position (batched launches)
   size_t scratch_stride = 0;
   size_t scratch_bytes = 0;
+  // mode-split fused form (tune.mode_groups > 1): groups per position, partial intensities,
+  // dl/dI frames and per-position validity of one chunk
+  int groups = 1;
+  int group_modes = 0;
+  float* ipart = nullptr;  // [fchunk][groups][NN]
+  float* cfr = nullptr;    // [fchunk][NN]
+  int* kvalid = nullptr;   // [fchunk]
   // per-step form
   int chunk = 0;
   float2* obuf = nullptr;

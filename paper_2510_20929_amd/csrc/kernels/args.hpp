@@ -58,6 +58,13 @@ struct CallArgs {
   int recompute;          // multislice: recompute incident waves instead of storing them
   int near;               // 1: near-field detector (Fresnel propagation, natural pixel order)
   int fshift;             // 1: Fourier-shift sub-pixel patch instead of bilinear
+  // mode-split form: the modes of a position are split into `groups` groups of at most
+  // `group_modes` modes, each group one work item (window index k * groups + g)
+  int groups;
+  int group_modes;
+  float* ipart;           // [K][groups][NN] partial intensities (frame layout: element i of thread t at i*T + t)
+  float* cfr;             // [K][NN] 2 dl/dI / (K_norm N^2) (same layout)
+  int* kvalid;            // [K] 1 where the position's window and loss are valid
 };
 
 }  // namespace ptyhip

@@ -17,12 +17,22 @@ __global__ __launch_bounds__(1024) void loss_reduce_kernel(const double* __restr
 
 __global__ void finalize_elems_kernel(FinalArgs f) {
   const size_t tid = size_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = size_t(gridDim.x) * blockDim.x;
+  // with rep > 1 every position has rep partial sums (one per mode group), added in order
+  const int rep = f.rep > 1 ? f.rep : 1;
   if (f.g_pos && f.pos_part)
-    for (size_t i = tid; i < size_t(f.K) * 2; i += stride)
-      f.g_pos[i] = f.accumulate ? f.g_pos[i] + float(f.pos_part[i]) : float(f.pos_part[i]);
+    for (size_t i = tid; i < size_t(f.K) * 2; i += stride) {
+      const size_t k = i / 2, c = i % 2;
+      double v = 0.0;
+      for (int g = 0; g < rep; ++g) v += f.pos_part[(k * rep + g) * 2 + c];
+      f.g_pos[i] = f.accumulate ? f.g_pos[i] + float(v) : float(v);
+    }
   if (f.g_w && f.w_part)
-    for (size_t i = tid; i < size_t(f.K) * f.E; i += stride)
-      f.g_w[i] = f.accumulate ? f.g_w[i] + float(f.w_part[i]) : float(f.w_part[i]);
+    for (size_t i = tid; i < size_t(f.K) * f.E; i += stride) {
+      const size_t k = i / f.E, e = i % f.E;
+      double v = 0.0;
+      for (int g = 0; g < rep; ++g) v += f.w_part[(k * rep + g) * f.E + e];
+      f.g_w[i] = f.accumulate ? f.g_w[i] + float(v) : float(v);
+    }
   if (f.g_probe && f.gprobe_part) {
     for (size_t i = tid; i < f.probe_elems; i += stride) {
       float2 s = f.accumulate ? f.g_probe[i] : make_float2(0.f, 0.f);

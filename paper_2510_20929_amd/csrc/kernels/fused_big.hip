@@ -81,6 +81,10 @@ __global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (!on[u]) continue;
+        if (w == nullptr) {  // no weights: one eigenprobe with weight 1
+          acc[0] = cadd(acc[0], v[u]);
+          continue;
+        }
         const float* wk = w + size_t(kk + u) * E;
 #pragma unroll
         for (int e = 0; e < 16; ++e)

@@ -5,7 +5,7 @@ namespace ptyhip {
 
 template <int TS>
 __global__ __launch_bounds__(256) void window_gather_kernel(GatherArgs g) {
-  gather_tile_t<float2, TS>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate);
+  gather_tile_t<float2, TS>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate, g.rep);
 }
 
 // 16 x 16 tiles unless the object has 8192 or more tiles of 32 x 32: a tile's windows are

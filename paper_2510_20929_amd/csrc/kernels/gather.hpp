@@ -27,10 +27,12 @@ template <> __device__ __forceinline__ float2 vzero<float2>() { return make_floa
 // hits at its 4 pixels, issuing the loads of 4 hits before adding them in order.
 // `win` holds [K][S][N+1][N+1] windows of value type V (float2 gradients, float
 // illumination), `out` the [S][H][W] result.
+// `rep` windows share one position (window k belongs to position k / rep; the mode-split
+// form writes one window per mode group).
 template <class V, int TS = GT>
 __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const int* __restrict__ wvalid,
                                               const float* __restrict__ pos, V* out_all, int K, int S, int N,
-                                              int H, int W, int accumulate) {
+                                              int H, int W, int accumulate, int rep = 1) {
   constexpr int CH = 1024;  // positions examined per chunk
   constexpr int NT = 256;
   __shared__ int hy[CH], hx[CH], hk[CH];
@@ -58,8 +60,9 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
       int y0 = 0, x0 = 0;
       bool hit = false;
       if (i < n && wvalid[k]) {
-        y0 = int(floorf(pos[2 * k]));
-        x0 = int(floorf(pos[2 * k + 1]));
+        const int kp = rep > 1 ? k / rep : k;
+        y0 = int(floorf(pos[2 * kp]));
+        x0 = int(floorf(pos[2 * kp + 1]));
         hit = !(y0 > ty0 + TS - 1 || y0 + WN - 1 < ty0 || x0 > tx0 + TS - 1 || x0 + WN - 1 < tx0);
       }
       const unsigned long long b = __ballot(hit);
@@ -113,7 +116,7 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
 }
 
 __device__ __forceinline__ void gather_tile(const GatherArgs& g) {
-  gather_tile_t<float2>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate);
+  gather_tile_t<float2>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate, g.rep);
 }
 
 }  // namespace ptyhip

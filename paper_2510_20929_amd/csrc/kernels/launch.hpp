@@ -35,6 +35,7 @@ struct FinalArgs {
   size_t probe_elems;
   int K, E;
   int accumulate;
+  int rep;                  // partial position / weight sums per position (0 or 1: one)
 };
 
 // Gather of the per-position window gradients into the object gradient.
@@ -56,10 +57,11 @@ struct IllumArgs {
 struct GatherArgs {
   const float2* gwin;  // [K][S][N+1][N+1]
   const int* wvalid;   // [K]
-  const float* pos;    // [K][2]
+  const float* pos;    // [K / rep][2]
   float2* gobj;        // [S][H][W]
-  int K, S, N, H, W;
+  int K, S, N, H, W;   // K: windows
   int accumulate;
+  int rep;             // windows per position (0 or 1: one)
 };
 
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st);
@@ -72,6 +74,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
                                  bool near = false, bool fshift = false);
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
 hipError_t launch_fused_small_fs(const CallArgs& a, int N, int threads, int grid, hipStream_t st);
+hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
 hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
                                      int accumulate, hipStream_t st);
 

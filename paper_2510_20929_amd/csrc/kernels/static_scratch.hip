@@ -205,7 +205,7 @@ extern "C" ptyhip_status ptyhip_forward_adjoint_static(const ptyhip_desc* desc, 
     if (launch_fused_small(c, N, t.variant, grid, st) != hipSuccess) return PTYHIP_EHIP;
     const bool add = acc || k0 > 0;
     if (want_obj) {
-      GatherArgs g;
+      GatherArgs g{};
       g.gwin = gwin;
       g.wvalid = wvalid;
       g.pos = c.pos;

@@ -53,7 +53,14 @@ class Desc(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32)]
+                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32), ("mode_groups", ctypes.c_int32)]
+
+
+def make_tune(tune: Optional[dict]) -> Optional["Tune"]:
+    """A ``Tune`` from a dict (variant, grid, recompute, plain_chunk, mode_groups; missing = 0)."""
+    if not tune:
+        return None
+    return Tune(*[int(tune.get(f, 0)) for f, _ in Tune._fields_])
 
 
 class PlanInfo(ctypes.Structure):
@@ -176,8 +183,7 @@ class Plan:
         self.max_positions = int(max_positions)
         h = ctypes.c_void_p()
         if tune:
-            tu = Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)),
-                      int(tune.get("recompute", 0)), int(tune.get("plain_chunk", 0)))
+            tu = make_tune(tune)
             st = _lib().ptyhip_plan_create_ex(ctypes.byref(self.desc), self.max_positions, ctypes.byref(tu),
                                               ctypes.byref(h))
         else:
@@ -376,8 +382,7 @@ class Batch:
         h = ctypes.c_void_p()
         tu = None
         if tune:
-            tu = ctypes.byref(Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)), int(tune.get("recompute", 0)),
-                                   int(tune.get("plain_chunk", 0))))
+            tu = ctypes.byref(make_tune(tune))
         _check(_lib().ptyhip_batch_create(descs, Ks, len(problems), tu, ctypes.byref(h)), "ptyhip_batch_create")
         self._h = h
         self.n = len(problems)
@@ -465,10 +470,7 @@ def forward_adjoint_static(desc: Desc, obj, probe, positions, I_meas, weights=No
     if I_pred is not None:
         _need(I_pred, "I_pred", torch.float32, (K, N, N))
         out["I_pred"] = I_pred
-    tu = None
-    if tune:
-        tu = ctypes.byref(Tune(int(tune.get("variant", 0)), int(tune.get("grid", 0)), int(tune.get("recompute", 0)),
-                               int(tune.get("plain_chunk", 0))))
+    tu = ctypes.byref(make_tune(tune)) if tune else None
     st = _lib().ptyhip_forward_adjoint_static(
         ctypes.byref(desc), tu, _stream(stream), K, flags, _ptr(obj), _ptr(probe), _ptr(weights), _ptr(positions),
         _ptr(I_meas), _ptr(out["loss"]), _ptr(I_pred), _ptr(out.get("g_obj")), _ptr(out.get("g_probe")),

@@ -98,3 +98,65 @@ def test_graph_replay_matches_direct_calls():
             assert torch.equal(r[key], o[key]), key
     assert plan.get_error() == 0
     plan.set_graphs(False)
+
+
+@pytest.mark.parametrize("M,E,G,N,loss", [(4, 1, 2, 128, "poisson"), (4, 1, 4, 128, "amplitude"),
+                                          (15, 3, 4, 128, "amplitude"), (15, 3, 15, 64, "poisson"),
+                                          (3, 2, 3, 32, "amplitude")])
+@pytest.mark.parametrize("variant", [0, 4])
+def test_mode_split_form(M, E, G, N, loss, variant):
+    """The mode-split form (each position's modes in G groups, three launches) against the
+    oracle, with eigenprobe weights or without, several groups of unequal size, every
+    gradient, on 8 workgroups (several items per workgroup)."""
+    from gpu_util import custom_problem
+    start, I = custom_problem(700 + M + E + G + N, N, M, E, 1, N * 3, 20, loss=loss,
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "mode_groups": G, "grid": 8}), start, I, grads)
+    compare(got, ref, grads, tag=f"split M={M} E={E} G={G} N={N} variant={variant}")
+    assert got["flags"] == 0
+
+
+def test_mode_split_forward_errors_and_accumulate():
+    """Mode-split form: the forward call alone (loss and predicted intensities), a position
+    whose window leaves the object (latched and dropped, the rest exact), and two shards
+    accumulated with the global normaliser equal to the whole."""
+    torch = torch_cuda()
+    import oracle
+    from gpu_util import custom_problem
+    start, I = custom_problem(731, 64, 6, 1, 1, 200, 24, loss="poisson")
+    tune = {"mode_groups": 3, "grid": 8}
+    plan = _plan(start, tune=tune)
+    o, u, r, m = dev(start.obj), dev(start.probe), dev(start.positions), dev(I)
+    ipred = torch.zeros((start.K, 64, 64), dtype=torch.float32, device="cuda")
+    loss = plan.forward(o, u, r, m, I_pred=ipred)
+    torch.cuda.synchronize()
+    ref_l, ref_I = oracle.forward(start.obj, start.probe, start.positions, I, loss=start.loss, eps=start.eps)
+    compare({"loss": float(loss.cpu()[0]), "I_pred": ipred.cpu().numpy()}, {"loss": ref_l, "I_pred": ref_I}, (),
+            tag="split forward")
+    # one position outside the object
+    bad = start.positions.copy()
+    bad[5] = (190.0, 3.0)
+    rb = dev(bad)
+    out = plan.forward_adjoint(o, u, rb, m, grads=("obj", "probe", "pos"))
+    torch.cuda.synchronize()
+    assert plan.get_error() & 1
+    plan.clear_error()
+    keep = np.array([k for k in range(start.K) if k != 5])
+    ref = run_oracle(start.subset(keep), I[keep], ("obj", "probe", "pos"), norm_count=start.K)
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    assert rel_l2(got["g_obj"], ref["g_obj"]) <= 1e-4
+    assert rel_l2(got["g_probe"], ref["g_probe"]) <= 1e-4
+    assert rel_l2(np.delete(got["g_pos"], 5, axis=0), ref["g_pos"]) <= 1e-4
+    assert np.all(got["g_pos"][5] == 0)
+    # shards with the global normaliser add up to the whole
+    sp = _plan(start, tune=tune, norm_count=start.K)
+    whole = sp.forward_adjoint(o, u, r, m, grads=("obj", "probe"))
+    acc = None
+    for a_, b_ in ((0, 7), (7, 24)):
+        acc = sp.forward_adjoint(o, u, r[a_:b_].contiguous(), m[a_:b_].contiguous(), grads=("obj", "probe"),
+                                 accumulate=acc is not None, out=None if acc is None else acc)
+    torch.cuda.synchronize()
+    for key in ("loss", "g_obj", "g_probe"):
+        assert rel_l2(acc[key].cpu().numpy(), whole[key].cpu().numpy()) <= 1e-5, key
