@@ -139,6 +139,10 @@ typedef struct {
                            few positions keep more workgroups busy; G is capped at the mode count;
                            forward and forward + adjoint calls only (the linear maps keep whole
                            positions). Other frames or models: PTYHIP_EUNSUPPORTED */
+  int32_t probe_stage;  /* 0: probe gradients staged per position only with several eigenprobes (or
+                           mode groups), else accumulated in each workgroup's scratch frames;
+                           1: always staged (each position writes its probe-wave gradients once,
+                           a separate pass adds them), one slice only */
 } ptyhip_tune;
 
 typedef struct {

@@ -79,7 +79,7 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE) -> None:
     os.replace(tmp, path)
 
 
-def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True) -> List[dict]:
+def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E: int = 1) -> List[dict]:
     """Thread layout x far-field store/recompute x persistent grid; with few positions per
     call and several modes (K below two workgroups per CU), also the mode-split form with
     enough groups to give every CU one or two (position, group) items."""
@@ -92,6 +92,13 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True) -
         for r in recomputes:
             for g in grids:
                 out.append({"variant": v, "recompute": r, "grid": g})
+    # single eigenprobe: the probe gradients staged per position instead of accumulated
+    # in the workgroups' scratch (a streaming write and a separate reduction in place of
+    # a read-modify-write per mode)
+    if S == 1 and E == 1:
+        for v in ([1, 4] if N in (64, 128) else [0]):
+            for r in recomputes:
+                out.append({"variant": v, "recompute": r, "grid": 0, "probe_stage": 1})
     if split_ok and N <= 128 and S == 1 and M > 1 and 0 < K < 2 * cus:
         groups = sorted({min(M, -(-c * cus // K)) for c in (1, 2)})
         for G in groups:
@@ -165,7 +172,7 @@ def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("
     results = []
     best = None
     split_ok = shape.get("det_lambda_z") is None and shape.get("subpixel", "bilinear") == "bilinear"
-    for cand in plan_candidates(shape["N"], shape["M"], shape["S"], K, split_ok):
+    for cand in plan_candidates(shape["N"], shape["M"], shape["S"], K, split_ok, shape["E"]):
         plan = make(cand)
         out = plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads)
         torch.cuda.synchronize()

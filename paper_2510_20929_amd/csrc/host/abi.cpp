@@ -162,7 +162,7 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   // position's probe-wave gradients and a separate pass forms sum_k w_k,e gP_k for every
   // eigenprobe (one write per pixel and mode instead of E read-modify-writes of the
   // workgroup's accumulator frames); chunk bounded to 2 GiB
-  const bool stage = S == 1 && (E > 1 || G > 1) && !p->whole_windows;
+  const bool stage = S == 1 && (E > 1 || G > 1 || p->tune.probe_stage == 1) && !p->whole_windows;
   if (stage) {
     const size_t per = size_t(M) * NN * sizeof(float2);
     p->fchunk = int(std::max<size_t>(1, std::min<size_t>(size_t(p->fchunk), win_budget / per)));
@@ -402,7 +402,8 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
   for (int k0 = 0; k0 < a.K; k0 += p->fchunk) {
     const int n = std::min(p->fchunk, a.K - k0);
     CallArgs c = chunk_args(a, k0, n, N, d.n_eig, d.n_modes);
-    const bool staged = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
+    const bool staged = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ &&
+                        (a.weights != nullptr || p->tune.probe_stage == 1);
     c.gpstage = staged ? p->gpstage : nullptr;
     timing_begin(p, st);
     hipError_t e = p->on_chip ? launch_fused_small(c, N, p->tune.variant, grid, st)
@@ -429,7 +430,8 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
                                 st) != hipSuccess)
       return PTYHIP_EHIP;
   }
-  const bool staged_all = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ && a.weights != nullptr;
+  const bool staged_all = want_probe && p->gpstage != nullptr && a.mode == MODE_FWD_ADJ &&
+                          (a.weights != nullptr || p->tune.probe_stage == 1);
   if (want_probe && !staged_all) {
     hipError_t e = p->on_chip
                        ? launch_probe_reduce_small(a, N, p->tune.variant, grid, reinterpret_cast<float2*>(g_probe),
@@ -590,7 +592,8 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
   if (tune && (tune->variant < 0 || tune->variant > (desc->frame <= 128 ? 4 : 1) || tune->grid < 0 ||
-               tune->plain_chunk < 0 || tune->recompute < 0 || tune->mode_groups < 0))
+               tune->plain_chunk < 0 || tune->recompute < 0 || tune->mode_groups < 0 || tune->probe_stage < 0 ||
+               tune->probe_stage > 1))
     return PTYHIP_EINVAL;
   if (tune && tune->mode_groups > 1 &&
       (desc->frame > 128 || desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||

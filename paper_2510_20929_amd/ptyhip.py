@@ -53,11 +53,13 @@ class Desc(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32), ("mode_groups", ctypes.c_int32)]
+                ("recompute", ctypes.c_int32), ("plain_chunk", ctypes.c_int32), ("mode_groups", ctypes.c_int32),
+                ("probe_stage", ctypes.c_int32)]
 
 
 def make_tune(tune: Optional[dict]) -> Optional["Tune"]:
-    """A ``Tune`` from a dict (variant, grid, recompute, plain_chunk, mode_groups; missing = 0)."""
+    """A ``Tune`` from a dict (variant, grid, recompute, plain_chunk, mode_groups, probe_stage;
+    missing = 0)."""
     if not tune:
         return None
     return Tune(*[int(tune.get(f, 0)) for f, _ in Tune._fields_])

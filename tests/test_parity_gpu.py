@@ -201,3 +201,16 @@ def test_config5_tuned_instance(which):
     got = run_gpu(_plan(start, tune=tune), start, I, grads)
     compare(got, ref, grads, tag=f"c5 {which} {tune}")
     assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("N,M,variant", [(128, 4, 4), (128, 4, 1), (64, 2, 0), (256, 2, 0), (512, 1, 0)])
+def test_probe_stage_single_eigenprobe(N, M, variant):
+    """Probe gradients staged per position (tune probe_stage) with one unweighted
+    eigenprobe, on 16 workgroups (several positions each), against the oracle."""
+    start, I = custom_problem(960 + N + M, N, M, 1, 1, N * 2 + 60, 40, loss="poisson")
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "recompute": 1, "grid": 16, "probe_stage": 1}), start, I,
+                  grads)
+    compare(got, ref, grads, tag=f"probe_stage N={N} M={M} variant={variant}")
+    assert got["flags"] == 0
