@@ -225,6 +225,20 @@ def measured_intensities(truth, dev, torch, t, Plan):
     return I
 
 
+def packing_bound(problems, cus):
+    """How much of the GPU one call per dataset leaves idle on uneven datasets: with one
+    position per workgroup per round, a call of K positions takes ceil(K / cus) rounds.
+    Position cost is modelled as modes x N^2 log2 N^2 (the transforms). Returns the
+    work-weighted occupancy of the per-call form and the gain a perfect packing of every
+    dataset's positions onto the workgroups would give over it (an upper bound for any
+    batched schedule)."""
+    cost = [p.M * p.N * p.N * math.log2(p.N * p.N) for p in problems]
+    work = sum(p.K * c for p, c in zip(problems, cost))
+    slots = sum(math.ceil(p.K / cus) * cus * c for p, c in zip(problems, cost))
+    return {"per_call_occupancy": work / slots, "perfect_packing_gain": slots / work, "workgroups": cus,
+            "cost_model": "positions x modes x N^2 log2 N^2, one position per workgroup per round"}
+
+
 def run_batched(args, dev, torch, t):
     """Config 4: one batched launch over 32 uneven datasets."""
     from paper_2510_20929_amd import Batch, Plan
@@ -273,6 +287,7 @@ def run_batched(args, dev, torch, t):
             "hbm": {"alg_GBs": byts / (ms * 1e-3) / 1e9, "frac_of_peak": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "per_call": {"value": K / (per_call_ms * 1e-3), "ms_per_step": per_call_ms},
             "batched_vs_per_call": per_call_ms / ms, "error_flags": b.get_error(),
+            "packing_bound": packing_bound(truths, torch.cuda.get_device_properties(0).multi_processor_count),
             "tune": choice, "tune_source": src,
             "config": {"datasets": len(truths), "positions": K,
                        "frames": sorted({p.N for p in truths}),

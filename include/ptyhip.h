@@ -132,13 +132,13 @@ typedef struct {
   int32_t recompute;    /* 1 = recompute (multislice: incident waves; several modes: far fields)
                            instead of keeping them in workgroup scratch */
   int32_t plain_chunk;  /* positions per chunk of the per-step path; 0 = auto */
-  int32_t mode_groups;  /* 0 or 1: a workgroup takes whole positions; G > 1 (on-chip frames, one
-                           slice, far field, bilinear patch): the modes of every position are split
+  int32_t mode_groups;  /* 0 or 1: a workgroup takes whole positions; G > 1 (one slice, far field,
+                           bilinear patch, any frame size): the modes of every position are split
                            into at most G groups, each (position, group) a work item of its own, in
-                           three launches (partial intensities, loss, adjoint), so that calls with
+                           three passes (partial intensities, loss, adjoint), so that calls with
                            few positions keep more workgroups busy; G is capped at the mode count;
                            forward and forward + adjoint calls only (the linear maps keep whole
-                           positions). Other frames or models: PTYHIP_EUNSUPPORTED */
+                           positions). Other models: PTYHIP_EUNSUPPORTED */
   int32_t probe_stage;  /* 0: probe gradients staged per position only with several eigenprobes (or
                            mode groups), else accumulated in each workgroup's scratch frames;
                            1: always staged (each position writes its probe-wave gradients once,

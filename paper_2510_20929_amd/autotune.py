@@ -99,7 +99,7 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E
         for v in ([1, 4] if N in (64, 128) else [0]):
             for r in recomputes:
                 out.append({"variant": v, "recompute": r, "grid": 0, "probe_stage": 1})
-    if split_ok and N <= 128 and S == 1 and M > 1 and 0 < K < 2 * cus:
+    if split_ok and S == 1 and M > 1 and 0 < K < 2 * cus:
         groups = sorted({min(M, -(-c * cus // K)) for c in (1, 2)})
         for G in groups:
             if G < 2:

@@ -175,6 +175,8 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
     if ((st = dalloc(p, &p->ipart, size_t(p->fchunk) * G * NN)) != PTYHIP_OK) return st;
     if ((st = dalloc(p, &p->cfr, size_t(p->fchunk) * NN)) != PTYHIP_OK) return st;
     if ((st = dalloc(p, &p->kvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
+    if (!p->on_chip && (st = dalloc(p, &p->lpart, size_t(p->fchunk) * split_loss_chunks(N))) != PTYHIP_OK)
+      return st;
   }
   if (stage) {
     if ((st = dalloc(p, &p->gpstage, size_t(p->fchunk) * M * NN)) != PTYHIP_OK) return st;
@@ -369,7 +371,8 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
       c.gwin = want_obj ? p->gwin : nullptr;
       c.wvalid = p->wvalid;
       timing_begin(p, st);
-      hipError_t e = launch_fused_split(c, N, p->tune.variant, p->grid, st);
+      hipError_t e = p->on_chip ? launch_fused_split(c, N, p->tune.variant, p->grid, st)
+                                : launch_fused_big_split(c, N, p->tune.variant, p->grid, p->lpart, st);
       timing_end(p, st);
       if (e != hipSuccess) return PTYHIP_EHIP;
       if (a.mode != MODE_FWD_ADJ) continue;
@@ -596,7 +599,7 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
                tune->probe_stage > 1))
     return PTYHIP_EINVAL;
   if (tune && tune->mode_groups > 1 &&
-      (desc->frame > 128 || desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||
+      (desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||
        desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR))
     return PTYHIP_EUNSUPPORTED;
   Plan* p = new (std::nothrow) Plan();

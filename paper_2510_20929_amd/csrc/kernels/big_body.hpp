@@ -76,8 +76,15 @@ inline size_t big_scratch_elems(int N, int M, int E, size_t* pacc_off) {
   return *pacc_off + nn * size_t(E) * M;
 }
 
-// Workgroup `wg` of `nwg` processes positions wg, wg + nwg, ... of the call `a`.
-template <int N, int TT, int LOSS>
+// Workgroup `wg` of `nwg` processes work items wg, wg + nwg, ... of the call `a`.
+// PH 0: an item is a position (every mode, loss and adjoint). The mode-split form
+// (a.groups > 1) makes every (position k, mode group g) pair an item k G + g and runs
+// in three passes: PH 1 writes the partial intensity sum_{m in g} |Psi_m|^2 of the item
+// (natural pixel order) to ipart; a loss pass sums a position's partials and writes
+// 2 dl/dI / (K_norm N^2) to cfr; PH 2 recomputes each far field of the group, scales it
+// by cfr, transforms it back and runs the inverse rows (staged probe-wave gradients,
+// window k G + g, per-item position and weight partial sums).
+template <int N, int TT, int LOSS, int PH = 0>
 __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh, int wg, int nwg) {
   using B = Big<N, TT>;
   constexpr int T = B::T, NN = B::NN, RB = B::RB, RP = B::RP, CP = B::CP, WN = B::WN, NB = B::NB;
@@ -123,7 +130,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
   const BufFrame gb(G, NN * 8);
   const BufFrame cfb(cf, NN * 4);
   const int v_win = (T >= N ? (tid / N) * a.W + tid % N : tid) * 8;
-  if ((a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH) && a.zero_acc && want_probe && !a.gpstage)
+  if (PH == 0 && (a.mode == MODE_FWD_ADJ || a.mode == MODE_APPLY_AH) && a.zero_acc && want_probe && !a.gpstage)
     for (size_t i = tid; i < size_t(a.E) * M * NN; i += T) pacc[i] = make_float2(0.f, 0.f);
   float2* tws = sh.tw;
   {
@@ -150,9 +157,31 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
     for (int j = 0; j < PER; ++j) t_col[j * CJ * CP] = fr.ld(v_col, (cb * RB + j * CJ * N) * 8);
   };
 
-  for (int k = wg; k < a.K; k += nwg) {
+  // work items: positions (PH 0) or (position, mode group) pairs (PH 1, 2)
+  const int NG = PH == 0 ? 1 : a.groups;
+  const int items = a.K * NG;
+  for (int it = wg; it < items; it += nwg) {
+    const int k = PH == 0 ? it : it / NG;
+    const int m0 = PH == 0 ? 0 : (it - k * NG) * a.group_modes;
+    const int m1 = PH == 0 ? M : min(M, m0 + a.group_modes);
+    if constexpr (PH == 2) {
+      if (!a.kvalid[k]) {
+        if (tid == 0) {
+          a.wvalid[it] = 0;
+          if (a.pos_part) {
+            a.pos_part[2 * size_t(it)] = 0.0;
+            a.pos_part[2 * size_t(it) + 1] = 0.0;
+          }
+        }
+        if (a.w_part && tid < a.E) a.w_part[size_t(it) * a.E + tid] = 0.0;
+        continue;
+      }
+    }
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
-    if (!p.ok) {
+    if constexpr (PH == 1) {
+      if (!p.ok) continue;  // the loss pass drops the position
+    }
+    if (PH == 0 && !p.ok) {
       if (tid == 0) {
         latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
         if (a.loss_part) a.loss_part[k] = 0.0;
@@ -217,26 +246,51 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         each(e, u);
       }
     };
+    // row transforms of the exit wave P_m o into the work frame
+    const auto exit_rows = [&](int m) {
+      for (int rb = 0; rb < NB; ++rb) {
+        for (int b0 = 0; b0 < PER; b0 += BAT) {
+          float2 P[BAT];
+          probe_batch(m, rb, b0, P, [](int, const float2(&)[BAT]) {});
+#pragma unroll
+          for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
+        }
+        __syncthreads();
+        B::LT::template run<false, true>(tile, RP, 1, tws);
+        __syncthreads();
+        rows_to_frame(rb);
+        __syncthreads();
+      }
+    };
 
-    if (fwd) {
+    if constexpr (PH == 1) {
+      // partial intensity of the group's modes, natural pixel order
+      const BufFrame ipb(a.ipart + size_t(it) * NN, NN * 4);
+      for (int m = m0; m < m1; ++m) {
+        exit_rows(m);
+        for (int cb = 0; cb < NB; ++cb) {
+          frame_to_cols(cb);
+          __syncthreads();
+          B::LT::template run<false, true>(tile, 1, CP, tws);
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < PER; ++j) {
+            const int so = cb * RB + j * CJ * N;
+            const float2 v = cscale(t_col[j * CJ * CP], inv_n);
+            ipb.stf((m == m0 ? 0.f : ipb.ldf(v_col / 2, so * 4)) + cabs2(v), v_col / 2, so * 4);
+          }
+          __syncthreads();
+        }
+      }
+      continue;
+    }
+
+    if (PH == 0 && fwd) {
       double lsum = 0.0;
       const float* im = a.imeas ? a.imeas + size_t(k) * NN : nullptr;
       for (int m = 0; m < M; ++m) {
         const bool last = m == M - 1;
-        // row transforms of the exit wave P_m o
-        for (int rb = 0; rb < NB; ++rb) {
-          for (int b0 = 0; b0 < PER; b0 += BAT) {
-            float2 P[BAT];
-            probe_batch(m, rb, b0, P, [](int, const float2(&)[BAT]) {});
-#pragma unroll
-            for (int j = 0; j < BAT; ++j) t_row[tro(b0 + j)] = cmul(P[j], patch(rb, b0 + j));
-          }
-          __syncthreads();
-          B::LT::template run<false, true>(tile, RP, 1, tws);
-          __syncthreads();
-          rows_to_frame(rb);
-          __syncthreads();
-        }
+        exit_rows(m);
         // column transforms: far field and intensity; the last mode also the loss, dl/dI
         // and (forward + adjoint) its own inverse column transforms
         for (int cb = 0; cb < NB; ++cb) {
@@ -315,36 +369,18 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       if (a.mode == MODE_FORWARD) continue;
     }
 
-    // adjoint, one mode at a time; forward + adjoint starts with the last mode, whose
-    // inverse column transforms the column pass has already done. The weight-gradient
-    // terms are summed per thread over a pixel batch, then per wave into the wave's own
-    // LDS slots (no atomics; the slots are added in a fixed order at the end).
+    // adjoint, one mode at a time. The weight-gradient terms are summed per thread over
+    // a pixel batch, then per wave into the wave's own LDS slots (no atomics; the slots
+    // are added in a fixed order at the end).
     const bool want_w = (a.want & WANT_WEIGHTS) && wk != nullptr;
     const int lane = tid & (WAVE - 1), wave = tid / WAVE;
-    float2* gwin = a.gwin ? a.gwin + size_t(k) * WN * WN : nullptr;
+    float2* gwin = a.gwin ? a.gwin + size_t(it) * WN * WN : nullptr;
     const bool want_obj = (a.want & WANT_OBJ) && gwin != nullptr;
     double gy = 0.0, gx = 0.0;
-    for (int jm = 0; jm < M; ++jm) {
-      const int m = fa ? (jm == 0 ? M - 1 : jm - 1) : jm;
-      const bool first = jm == 0, lastj = jm == M - 1;
-      if (!(fa && first)) {
-        // inverse column transforms of the scaled far field (or of the given far field)
-        const BufFrame src(fa ? Ps + size_t(m) * NN : a.Y + (size_t(k) * M + m) * NN, NN * 8);
-        for (int cb = 0; cb < NB; ++cb) {
-#pragma unroll
-          for (int j = 0; j < PER; ++j) {
-            const int so = cb * RB + j * CJ * N;
-            const float2 v = src.ld(v_col, so * 8);
-            t_col[j * CJ * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
-          }
-          __syncthreads();
-          B::LT::template run<true, true>(tile, 1, CP, tws);
-          __syncthreads();
-          cols_to_frame(cb);
-          __syncthreads();
-        }
-      }
-      // inverse row transforms, conjugate multiplies, probe-side gradients
+    // inverse row transforms of mode m from the work frame, conjugate multiplies,
+    // probe-side gradients; the patch gradient summed over the modes so far stays in G
+    // until the last one, whose rows give the window gradient and position terms
+    const auto adjoint_rows = [&](int m, bool first, bool lastj) {
       const BufFrame stage(a.gpstage ? a.gpstage + (size_t(k) * M + m) * NN : Fr, NN * 8);
       for (int rb = 0; rb < NB; ++rb) {
         frame_to_rows(rb);
@@ -383,7 +419,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
             t_row[tro(b0 + j)] = go;
             if (want_probe && a.gpstage) {
               stage.st(gP[j], v_row, so * 8);
-            } else if (want_probe) {
+            } else if (PH == 0 && want_probe) {
               const int ne = wk ? a.E : 1;
               for (int e = 0; e < ne; ++e) {
                 float2& acc = pacc[(size_t(e) * M + m) * NN + tid + so];
@@ -432,14 +468,66 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
         }
         __syncthreads();
       }
+    };
+
+    if constexpr (PH == 2) {
+      // per mode of the group: far field recomputed, scaled by 2 dl/dI / (K_norm N^2) of
+      // the loss pass and transformed back on the same column tile, then the inverse rows
+      const BufFrame cfrb(a.cfr + size_t(k) * NN, NN * 4);
+      for (int m = m0; m < m1; ++m) {
+        exit_rows(m);
+        for (int cb = 0; cb < NB; ++cb) {
+          frame_to_cols(cb);
+          __syncthreads();
+          B::LT::template run<false, true>(tile, 1, CP, tws);
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < PER; ++j) {
+            const int so = cb * RB + j * CJ * N;
+            float2& tv = t_col[j * CJ * CP];
+            tv = cscale(tv, inv_n * cfrb.ldf(v_col / 2, so * 4));
+          }
+          __syncthreads();
+          B::LT::template run<true, true>(tile, 1, CP, tws);
+          __syncthreads();
+          cols_to_frame(cb);
+          __syncthreads();
+        }
+        adjoint_rows(m, m == m0, m == m1 - 1);
+      }
+    } else {
+      // forward + adjoint starts with the last mode, whose inverse column transforms the
+      // column pass has already done
+      for (int jm = 0; jm < M; ++jm) {
+        const int m = fa ? (jm == 0 ? M - 1 : jm - 1) : jm;
+        const bool first = jm == 0, lastj = jm == M - 1;
+        if (!(fa && first)) {
+          // inverse column transforms of the scaled far field (or of the given far field)
+          const BufFrame src(fa ? Ps + size_t(m) * NN : a.Y + (size_t(k) * M + m) * NN, NN * 8);
+          for (int cb = 0; cb < NB; ++cb) {
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+              const int so = cb * RB + j * CJ * N;
+              const float2 v = src.ld(v_col, so * 8);
+              t_col[j * CJ * CP] = fa ? cscale(v, a.gscale * cfb.ldf(v_col / 2, so * 4)) : v;
+            }
+            __syncthreads();
+            B::LT::template run<true, true>(tile, 1, CP, tws);
+            __syncthreads();
+            cols_to_frame(cb);
+            __syncthreads();
+          }
+        }
+        adjoint_rows(m, first, lastj);
+      }
     }
 
     if (want_pos && a.pos_part) {
       double v[2] = {gy, gx};
       block_sum_n<T, 2>(v, red);
       if (tid == 0) {
-        a.pos_part[2 * k] = v[0];
-        a.pos_part[2 * k + 1] = v[1];
+        a.pos_part[2 * size_t(it)] = v[0];
+        a.pos_part[2 * size_t(it) + 1] = v[1];
       }
     }
     if (want_w) {
@@ -451,8 +539,8 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
       }
     }
     __syncthreads();
-    if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights && tid < a.E) a.w_part[size_t(k) * a.E + tid] = wacc[tid];
-    if (tid == 0 && a.wvalid) a.wvalid[k] = 1;
+    if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights && tid < a.E) a.w_part[size_t(it) * a.E + tid] = wacc[tid];
+    if (tid == 0 && a.wvalid) a.wvalid[it] = 1;
   }
 }
 

@@ -123,6 +123,103 @@ hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* 
   return hipGetLastError();
 }
 
+// Mode-split form (a.groups > 1) of the four-step body: forward pass (PH 1) and adjoint
+// pass (PH 2) over (position, mode group) items; the loss pass between them is
+// split_loss_nat_kernel + split_loss_total_kernel.
+template <int N, int T, int PH>
+__global__ __launch_bounds__(T) void split_big_kernel(CallArgs a) {
+  __shared__ BigShared<N, T> sh;
+  big_body<N, T, 0, PH>(a, sh, blockIdx.x, gridDim.x);
+}
+
+// Loss pass of the mode-split form for frames in natural pixel order. Block (c, k) takes
+// pixels [c SPLIT_LOSS_PIX, (c + 1) SPLIT_LOSS_PIX) of position k: I = the sum of the
+// position's partial intensities in group order, the loss against the DC-centred
+// measurement, I_pred, and cfr = 2 dl/dI / (K_norm N^2) (already scaled by gscale); its
+// loss sum goes to lpart[k][c].
+constexpr int SPLIT_LOSS_PIX = 16384;
+
+template <int LOSS>
+__global__ __launch_bounds__(1024) void split_loss_nat_kernel(CallArgs a, int N, double* __restrict__ lpart) {
+  __shared__ double red[2 * (1024 / WAVE)];
+  const int c = blockIdx.x, nch = gridDim.x;
+  const size_t NN = size_t(N) * N;
+  const int p0 = c * SPLIT_LOSS_PIX, p1 = min(int(NN), p0 + SPLIT_LOSS_PIX);
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  for (int k = blockIdx.y; k < a.K; k += gridDim.y) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    double lsum = 0.0;
+    if (p.ok) {
+      const float* ip = a.ipart + size_t(k) * a.groups * NN;
+      for (int pix = p0 + int(threadIdx.x); pix < p1; pix += 1024) {
+        float I = 0.f;
+        for (int g = 0; g < a.groups; ++g) I += ip[size_t(g) * NN + pix];
+        const int ci = centred_index(pix / N, pix % N, N);
+        float l, cc;
+        loss_terms<LOSS>(I, a.imeas[size_t(k) * NN + ci], a.eps, l, cc);
+        lsum += double(l);
+        if (a.ipred) a.ipred[size_t(k) * NN + ci] = I;
+        if (a.cfr) a.cfr[size_t(k) * NN + pix] = a.gscale * cc;
+      }
+    } else if (a.ipred) {
+      for (int pix = p0 + int(threadIdx.x); pix < p1; pix += 1024) a.ipred[size_t(k) * NN + pix] = 0.f;
+    }
+    const double tot = block_sum<1024>(lsum, red);
+    if (threadIdx.x == 0) lpart[size_t(k) * nch + c] = tot;
+  }
+}
+
+// per position: the chunk sums in order, the finiteness check, the validity the adjoint
+// pass reads, and the error latch for positions outside the object or non-finite
+__global__ __launch_bounds__(256) void split_loss_total_kernel(CallArgs a, int N, int nch,
+                                                               const double* __restrict__ lpart) {
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.K; k += gridDim.x * blockDim.x) {
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) {
+      latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
+      a.loss_part[k] = 0.0;
+      a.kvalid[k] = 0;
+      continue;
+    }
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += lpart[size_t(k) * nch + c];
+    const bool fin = isfinite(s);
+    a.loss_part[k] = fin ? s * double(a.lscale) : 0.0;
+    a.kvalid[k] = fin ? 1 : 0;
+    if (!fin) latch(a.flags, FLAG_NONFINITE);
+  }
+}
+
+int split_loss_chunks(int N) { return (N * N + SPLIT_LOSS_PIX - 1) / SPLIT_LOSS_PIX; }
+
+template <int N, int T>
+static hipError_t launch_big_split_t(const CallArgs& a, int grid_items, double* lpart, hipStream_t st) {
+  hipLaunchKernelGGL((split_big_kernel<N, T, 1>), dim3(grid_items), dim3(T), 0, st, a);
+  const dim3 lg(unsigned(split_loss_chunks(N)), unsigned(a.K < 65535 ? a.K : 65535));
+  if (a.loss == 0) hipLaunchKernelGGL(split_loss_nat_kernel<0>, lg, dim3(1024), 0, st, a, N, lpart);
+  else hipLaunchKernelGGL(split_loss_nat_kernel<1>, lg, dim3(1024), 0, st, a, N, lpart);
+  hipLaunchKernelGGL(split_loss_total_kernel, dim3(unsigned((a.K + 255) / 256)), dim3(256), 0, st, a, N,
+                     split_loss_chunks(N), (const double*)lpart);
+  if (a.mode == MODE_FWD_ADJ) hipLaunchKernelGGL((split_big_kernel<N, T, 2>), dim3(grid_items), dim3(T), 0, st, a);
+  return hipGetLastError();
+}
+
+// The passes of one chunk of positions in the mode-split form; `grid` bounds the
+// workgroups of the forward and adjoint passes (at most one per item).
+hipError_t launch_fused_big_split(const CallArgs& a, int N, int variant, int grid, double* lpart, hipStream_t st) {
+  if (a.K <= 0) return hipSuccess;
+  if (a.S != 1) return hipErrorNotSupported;
+  const int items = a.K * a.groups;
+  const int gi = grid < items ? (grid > 0 ? grid : 1) : items;
+  const bool two = variant == 1;
+  switch (N) {
+    case 256: return two ? launch_big_split_t<256, 512>(a, gi, lpart, st) : launch_big_split_t<256, 1024>(a, gi, lpart, st);
+    case 512: return two ? launch_big_split_t<512, 256>(a, gi, lpart, st) : launch_big_split_t<512, 1024>(a, gi, lpart, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int N, int T>
 static hipError_t launch_big_t(const CallArgs& a, int grid, hipStream_t st) {
   if (a.loss == 0) hipLaunchKernelGGL((fused_big_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);

@@ -82,6 +82,9 @@ size_t fused_big_scratch_elems(int N, int S, int M, int E, size_t* pacc_off);
 int fused_big_threads(int N, int variant);
 int fused_big_wg_per_cu(int variant);
 hipError_t launch_fused_big(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
+// mode-split form of the four-step body; lpart: [K][split_loss_chunks(N)] loss partials
+int split_loss_chunks(int N);
+hipError_t launch_fused_big_split(const CallArgs& a, int N, int variant, int grid, double* lpart, hipStream_t st);
 hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* valid, int n, int E, int M, int N,
                                    int splits, float2* part, float2* g_probe, int accumulate, hipStream_t st);
 hipError_t launch_probe_reduce_big(const CallArgs& a, int N, int grid, float2* g_probe, int accumulate,

@@ -118,18 +118,37 @@ def test_mode_split_form(M, E, G, N, loss, variant):
     assert got["flags"] == 0
 
 
-def test_mode_split_forward_errors_and_accumulate():
-    """Mode-split form: the forward call alone (loss and predicted intensities), a position
-    whose window leaves the object (latched and dropped, the rest exact), and two shards
-    accumulated with the global normaliser equal to the whole."""
+@pytest.mark.parametrize("M,E,G,N,loss,variant", [(3, 1, 3, 256, "poisson", 0), (4, 2, 2, 256, "amplitude", 1),
+                                                  (5, 3, 2, 512, "amplitude", 0), (3, 1, 3, 512, "poisson", 1)])
+def test_mode_split_form_fourstep(M, E, G, N, loss, variant):
+    """The mode-split form of the four-step kernel (256^2, 512^2 frames) against the
+    oracle: groups of one or several modes (unequal sizes for M = 5, G = 2), eigenprobe
+    weights or none, every gradient, both thread layouts, on 6 workgroups so that each
+    takes several (position, group) items."""
+    from gpu_util import custom_problem
+    start, I = custom_problem(760 + M + E + G + N, N, M, E, 1, N + 96, 9, loss=loss,
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": variant, "mode_groups": G, "grid": 6}), start, I, grads)
+    compare(got, ref, grads, tag=f"split four-step M={M} E={E} G={G} N={N} variant={variant}")
+    assert got["flags"] == 0
+
+
+@pytest.mark.parametrize("N,H", [(64, 200), (256, 360)])
+def test_mode_split_forward_errors_and_accumulate(N, H):
+    """Mode-split form (on-chip and four-step frames): the forward call alone (loss and
+    predicted intensities), a position whose window leaves the object (latched and
+    dropped, the rest exact), and two shards accumulated with the global normaliser equal
+    to the whole."""
     torch = torch_cuda()
     import oracle
     from gpu_util import custom_problem
-    start, I = custom_problem(731, 64, 6, 1, 1, 200, 24, loss="poisson")
+    start, I = custom_problem(731, N, 6, 1, 1, H, 24 if N <= 128 else 10, loss="poisson")
     tune = {"mode_groups": 3, "grid": 8}
     plan = _plan(start, tune=tune)
     o, u, r, m = dev(start.obj), dev(start.probe), dev(start.positions), dev(I)
-    ipred = torch.zeros((start.K, 64, 64), dtype=torch.float32, device="cuda")
+    ipred = torch.zeros((start.K, N, N), dtype=torch.float32, device="cuda")
     loss = plan.forward(o, u, r, m, I_pred=ipred)
     torch.cuda.synchronize()
     ref_l, ref_I = oracle.forward(start.obj, start.probe, start.positions, I, loss=start.loss, eps=start.eps)
@@ -137,7 +156,7 @@ def test_mode_split_forward_errors_and_accumulate():
             tag="split forward")
     # one position outside the object
     bad = start.positions.copy()
-    bad[5] = (190.0, 3.0)
+    bad[5] = (H - 10.0, 3.0)
     rb = dev(bad)
     out = plan.forward_adjoint(o, u, rb, m, grads=("obj", "probe", "pos"))
     torch.cuda.synchronize()
@@ -154,7 +173,7 @@ def test_mode_split_forward_errors_and_accumulate():
     sp = _plan(start, tune=tune, norm_count=start.K)
     whole = sp.forward_adjoint(o, u, r, m, grads=("obj", "probe"))
     acc = None
-    for a_, b_ in ((0, 7), (7, 24)):
+    for a_, b_ in ((0, 7), (7, start.K)):
         acc = sp.forward_adjoint(o, u, r[a_:b_].contiguous(), m[a_:b_].contiguous(), grads=("obj", "probe"),
                                  accumulate=acc is not None, out=None if acc is None else acc)
     torch.cuda.synchronize()
