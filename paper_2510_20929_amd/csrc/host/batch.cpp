@@ -292,6 +292,19 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
   });
   std::vector<BatchEntry> sorted(b->n);
   for (int j = 0; j < b->n; ++j) sorted[j] = b->tab[order[j]];
+  // the gather launch of a class: each dataset with an object gradient owns a range of
+  // its workgroups, one per tile
+  for (int j = 0, tile = 0; j < b->n; ++j) {
+    BatchEntry& e = sorted[j];
+    if (j > 0 && batch_class(e.N) != batch_class(sorted[j - 1].N)) tile = 0;
+    e.first_tile = tile;
+    if (e.g.gobj) {
+      e.gts = gather_tile_side(e.g.H, e.g.W, e.g.S);
+      e.tiles_x = (e.g.W + e.gts - 1) / e.gts;
+      e.tiles_y = (e.g.H + e.gts - 1) / e.gts;
+      tile += e.tiles_x * e.tiles_y * e.g.S;
+    }
+  }
   if (!b->uploaded || std::memcmp(sorted.data(), b->staging, sizeof(BatchEntry) * b->n) != 0) {
     // the previous upload may still be in flight or in use: wait for the stream first
     if (hipStreamSynchronize(st) != hipSuccess) return PTYHIP_EHIP;

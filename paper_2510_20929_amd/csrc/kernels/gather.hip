@@ -8,12 +8,8 @@ __global__ __launch_bounds__(256) void window_gather_kernel(GatherArgs g) {
   gather_tile_t<float2, TS>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate, g.rep);
 }
 
-// 16 x 16 tiles unless the object has 8192 or more tiles of 32 x 32: a tile's windows are
-// walked one after the other, so smaller tiles keep more CUs busy with shorter walks
-// (measured faster for objects of 256^2 to 2048^2); very large objects keep 32 x 32
 hipError_t launch_window_gather(const GatherArgs& g, hipStream_t st) {
-  const size_t tiles = size_t((g.W + GT - 1) / GT) * size_t((g.H + GT - 1) / GT) * size_t(g.S);
-  if (tiles < 8192) {
+  if (gather_tile_side(g.H, g.W, g.S) < GT) {
     constexpr int TS = GT / 2;
     dim3 grid(unsigned((g.W + TS - 1) / TS), unsigned((g.H + TS - 1) / TS), unsigned(g.S));
     hipLaunchKernelGGL(window_gather_kernel<TS>, grid, dim3(256), 0, st, g);

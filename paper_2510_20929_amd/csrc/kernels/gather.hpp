@@ -11,8 +11,6 @@
 
 namespace ptyhip {
 
-constexpr int GT = 32;  // tile side
-
 __device__ __forceinline__ float vadd(float a, float b) { return a + b; }
 __device__ __forceinline__ float2 vadd(float2 a, float2 b) { return cadd(a, b); }
 template <class V> __device__ __forceinline__ V vzero();
@@ -29,10 +27,11 @@ template <> __device__ __forceinline__ float2 vzero<float2>() { return make_floa
 // illumination), `out` the [S][H][W] result.
 // `rep` windows share one position (window k belongs to position k / rep; the mode-split
 // form writes one window per mode group).
+// The tile is (bx, by) of slice bz.
 template <class V, int TS = GT>
-__device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const int* __restrict__ wvalid,
-                                              const float* __restrict__ pos, V* out_all, int K, int S, int N,
-                                              int H, int W, int accumulate, int rep = 1) {
+__device__ __forceinline__ void gather_tile_at(const V* __restrict__ win, const int* __restrict__ wvalid,
+                                               const float* __restrict__ pos, V* out_all, int K, int S, int N,
+                                               int H, int W, int accumulate, int rep, int bx, int by, int bz) {
   constexpr int CH = 1024;  // positions examined per chunk
   constexpr int NT = 256;
   __shared__ int hy[CH], hx[CH], hk[CH];
@@ -41,7 +40,7 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
   constexpr int PJ = TS / RPP;   // passes (pixels per thread)
   static_assert(RPP * TS == NT && PJ * RPP == TS, "the tile must split evenly over the threads");
   const int WN = N + 1;
-  const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS, s = blockIdx.z;
+  const int tx0 = bx * TS, ty0 = by * TS, s = bz;
   const int c = threadIdx.x % TS, r0 = threadIdx.x / TS;
   const int x = tx0 + c;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -115,8 +114,14 @@ __device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const i
   }
 }
 
-__device__ __forceinline__ void gather_tile(const GatherArgs& g) {
-  gather_tile_t<float2>(g.gwin, g.wvalid, g.pos, g.gobj, g.K, g.S, g.N, g.H, g.W, g.accumulate, g.rep);
+// the tile of this workgroup: (blockIdx.x, blockIdx.y) of slice blockIdx.z
+template <class V, int TS = GT>
+__device__ __forceinline__ void gather_tile_t(const V* __restrict__ win, const int* __restrict__ wvalid,
+                                              const float* __restrict__ pos, V* out_all, int K, int S, int N,
+                                              int H, int W, int accumulate, int rep = 1) {
+  gather_tile_at<V, TS>(win, wvalid, pos, out_all, K, S, N, H, W, accumulate, rep, blockIdx.x, blockIdx.y,
+                        blockIdx.z);
 }
+
 
 }  // namespace ptyhip

@@ -64,6 +64,16 @@ struct GatherArgs {
   int rep;             // windows per position (0 or 1: one)
 };
 
+constexpr int GT = 32;  // largest gather tile side
+
+// tile side of the window gather: 16 unless the object has 8192 or more tiles of 32 x 32
+// (a tile's windows are walked one after the other, so smaller tiles keep more CUs busy
+// with shorter walks; measured faster for objects of 256^2 to 2048^2)
+inline int gather_tile_side(int H, int W, int S) {
+  const size_t tiles = size_t((W + GT - 1) / GT) * size_t((H + GT - 1) / GT) * size_t(S);
+  return tiles < 8192 ? GT / 2 : GT;
+}
+
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st);
 hipError_t launch_window_gather(const GatherArgs& g, hipStream_t st);
 hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inverse, hipStream_t st);
@@ -111,6 +121,10 @@ struct BatchEntry {
   int first_wg;      // first workgroup of the dataset in the batched launch
   int n_wg;          // workgroups assigned to the dataset
   int N;             // frame size
+  int first_tile;    // first workgroup of the dataset in its class's gather launch
+  int tiles_x;       // gather tiles per object row, per column (0: no gather)
+  int tiles_y;
+  int gts;           // gather tile side (16 or 32)
   int pad;
 };
 
