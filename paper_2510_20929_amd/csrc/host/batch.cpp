@@ -109,13 +109,13 @@ ptyhip_status ptyhip_batch_create(const ptyhip_desc* descs, const int32_t* K, in
   const int grid_total = (tune && tune->grid > 0) ? int(tune->grid) : prop.multiProcessorCount;
   double cls_cost[BATCH_CLASSES] = {}, all_cost = 0.0;
   for (int i = 0; i < n; ++i) {
-    cls_cost[batch_class(descs[i].frame)] += cost[i];
+    cls_cost[batch_class(descs[i].frame, descs[i].loss)] += cost[i];
     all_cost += cost[i];
   }
   for (int c = 0; c < BATCH_CLASSES; ++c) {
     std::vector<int> members;
     for (int i = 0; i < n; ++i)
-      if (batch_class(descs[i].frame) == c) members.push_back(i);
+      if (batch_class(descs[i].frame, descs[i].loss) == c) members.push_back(i);
     const int nc = int(members.size());
     b->cls_count[c] = nc;
     if (nc == 0) continue;
@@ -287,7 +287,7 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
   std::vector<int> order(b->n);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int x, int y) {
-    const int cx = batch_class(b->tab[x].N), cy = batch_class(b->tab[y].N);
+    const int cx = batch_class(b->tab[x].N, b->tab[x].a.loss), cy = batch_class(b->tab[y].N, b->tab[y].a.loss);
     return cx != cy ? cx < cy : b->first_wg[x] < b->first_wg[y];
   });
   std::vector<BatchEntry> sorted(b->n);
@@ -296,7 +296,7 @@ ptyhip_status ptyhip_batch_launch(ptyhip_batch bh, void* stream, uint32_t flags)
   // its workgroups, one per tile
   for (int j = 0, tile = 0; j < b->n; ++j) {
     BatchEntry& e = sorted[j];
-    if (j > 0 && batch_class(e.N) != batch_class(sorted[j - 1].N)) tile = 0;
+    if (j > 0 && batch_class(e.N, e.a.loss) != batch_class(sorted[j - 1].N, sorted[j - 1].a.loss)) tile = 0;
     e.first_tile = tile;
     if (e.g.gobj) {
       e.gts = gather_tile_side(e.g.H, e.g.W, e.g.S);

@@ -1,8 +1,10 @@
 // Many independent reconstructions of uneven frame size in a few persistent launches.
 //
-// Datasets are grouped by frame size (64^2, 128^2, 256^2, 512^2) and each class runs as
-// one persistent launch with that class's thread layout. A launch's workgroups are partitioned among its datasets in proportion
-// to their work (positions x modes x transform cost); every workgroup reads its
+// Datasets are grouped by frame size (64^2, 128^2, 256^2, 512^2) and loss form, and each
+// class runs as one persistent launch with that frame size's thread layout (the loss form
+// a compile-time choice, as in the per-plan kernels). A launch's workgroups are
+// partitioned among its datasets in proportion to their work (positions x modes x
+// transform cost); every workgroup reads its
 // dataset's call arguments from a device descriptor table (sorted by class, then by
 // first workgroup) and runs the same per-position body as the per-plan kernels (512
 // threads for 64^2; 1024 for 128^2, with the patch in registers, and for the four-step
@@ -29,35 +31,34 @@ __device__ __forceinline__ int batch_dataset(const BatchEntry* __restrict__ tab,
   return d;
 }
 
+template <int LOSS>
 __global__ __launch_bounds__(BT) void batched_64_kernel(const BatchEntry* __restrict__ tab, int n) {
   __shared__ SmallShared<64, BT> sh;
   const int d = batch_dataset(tab, n);
   const CallArgs a = tab[d].a;
   const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
-  if (a.loss == 0) small_body<64, BT, 0>(a, sh, wg, nwg);
-  else small_body<64, BT, 1>(a, sh, wg, nwg);
+  small_body<64, BT, LOSS>(a, sh, wg, nwg);
 }
 
+template <int LOSS>
 __global__ __launch_bounds__(BT128) void batched_128_kernel(const BatchEntry* __restrict__ tab, int n) {
   __shared__ SmallShared<128, BT128> sh;
   const int d = batch_dataset(tab, n);
   const CallArgs a = tab[d].a;
   const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
-  if (a.loss == 0) small_body<128, BT128, 0, true, false>(a, sh, wg, nwg);
-  else small_body<128, BT128, 1, true, false>(a, sh, wg, nwg);
+  small_body<128, BT128, LOSS, true, false>(a, sh, wg, nwg);
 }
 
-template <int N, int T>
+template <int N, int T, int LOSS>
 __global__ __launch_bounds__(T) void batched_big_kernel(const BatchEntry* __restrict__ tab, int n) {
   __shared__ BigShared<N, T> sh;
   const int d = batch_dataset(tab, n);
   const CallArgs a = tab[d].a;
   const int wg = int(blockIdx.x) - tab[d].first_wg, nwg = tab[d].n_wg;
-  if (a.loss == 0) big_body<N, T, 0>(a, sh, wg, nwg);
-  else big_body<N, T, 1>(a, sh, wg, nwg);
+  big_body<N, T, LOSS>(a, sh, wg, nwg);
 }
 
-int batch_class(int N) { return N <= 64 ? 0 : (N == 128 ? 1 : (N == 256 ? 2 : 3)); }
+int batch_class(int N, int loss) { return 2 * (N <= 64 ? 0 : (N == 128 ? 1 : (N == 256 ? 2 : 3))) + (loss ? 1 : 0); }
 
 int batch_variant(int N) { return N == 128 ? 4 : 0; }
 
@@ -134,10 +135,14 @@ hipError_t launch_batched_class(const BatchEntry* dev_tab, const BatchEntry* hos
   const BatchEntry* h = host_tab + cls_first[c];
   const dim3 grid{unsigned(cls_wg[c])};
   switch (c) {
-    case 0: hipLaunchKernelGGL(batched_64_kernel, grid, dim3(BT), 0, st, t, nc); break;
-    case 1: hipLaunchKernelGGL(batched_128_kernel, grid, dim3(BT128), 0, st, t, nc); break;
-    case 2: hipLaunchKernelGGL((batched_big_kernel<256, 1024>), grid, dim3(1024), 0, st, t, nc); break;
-    default: hipLaunchKernelGGL((batched_big_kernel<512, 1024>), grid, dim3(1024), 0, st, t, nc); break;
+    case 0: hipLaunchKernelGGL(batched_64_kernel<0>, grid, dim3(BT), 0, st, t, nc); break;
+    case 1: hipLaunchKernelGGL(batched_64_kernel<1>, grid, dim3(BT), 0, st, t, nc); break;
+    case 2: hipLaunchKernelGGL(batched_128_kernel<0>, grid, dim3(BT128), 0, st, t, nc); break;
+    case 3: hipLaunchKernelGGL(batched_128_kernel<1>, grid, dim3(BT128), 0, st, t, nc); break;
+    case 4: hipLaunchKernelGGL((batched_big_kernel<256, 1024, 0>), grid, dim3(1024), 0, st, t, nc); break;
+    case 5: hipLaunchKernelGGL((batched_big_kernel<256, 1024, 1>), grid, dim3(1024), 0, st, t, nc); break;
+    case 6: hipLaunchKernelGGL((batched_big_kernel<512, 1024, 0>), grid, dim3(1024), 0, st, t, nc); break;
+    default: hipLaunchKernelGGL((batched_big_kernel<512, 1024, 1>), grid, dim3(1024), 0, st, t, nc); break;
   }
   int tiles = 0;
   size_t nel = 0;

@@ -129,10 +129,11 @@ struct BatchEntry {
 };
 
 size_t batched_scratch_elems(int N, int M, int E, int recompute, size_t* pacc_off);
-// frame-size classes of the batched launch: 64^2, 128^2, 256^2, 512^2, and the tuning
-// variant whose body (and scratch layout) each class runs
-constexpr int BATCH_CLASSES = 4;
-int batch_class(int N);
+// classes of the batched launch: frame size (64^2, 128^2, 256^2, 512^2) x loss form
+// (amplitude, Poisson), class 2 * size + loss; and the tuning variant whose body (and
+// scratch layout) each frame size runs
+constexpr int BATCH_CLASSES = 8;
+int batch_class(int N, int loss);
 int batch_variant(int N);
 hipError_t launch_batched(const BatchEntry* dev_tab, const BatchEntry* host_tab, int n, const int* cls_first,
                           const int* cls_count, const int* cls_wg, hipStream_t st);
