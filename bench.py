@@ -199,6 +199,13 @@ def build_workload(name):
 def kernel_name(plan, prob, tune):
     info = plan.info()
     loss = 1 if prob.loss == "poisson" else 0
+    groups = int((tune or {}).get("mode_groups", 0) or 0)
+    if groups > 1 and prob.M > 1:
+        # mode-split form: three passes per chunk, timed together
+        if prob.N >= 256:
+            return "split_big_kernel<%d, %d, 1/2> + split_loss_nat_kernel<%d> (mode groups %d)" % (
+                prob.N, info["threads"], loss, groups)
+        return "split_forward/loss/adjoint_kernel<%d, %d> (mode groups %d)" % (prob.N, info["threads"], groups)
     if prob.N >= 256:
         return "fused_big_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     if prob.S > 1:
