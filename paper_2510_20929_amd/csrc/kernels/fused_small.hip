@@ -36,7 +36,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
   __shared__ float2 tws[N];
   __shared__ double red[2 * (T / WAVE)];
   __shared__ float wsh[MAX_EIG];
-  __shared__ double wacc[MAX_EIG];
+  __shared__ double wacc[MAX_EIG * (T / WAVE)];
   const int tid = threadIdx.x;
   const int S = a.S;
   for (int i = threadIdx.x; i < N; i += T) tws[i] = a.tw[i];
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
     }
     __syncthreads();
     if (a.weights && tid < a.E) wsh[tid] = a.weights[size_t(k) * a.E + tid];
-    if (tid < MAX_EIG) wacc[tid] = 0.0;
+    for (int i = tid; i < MAX_EIG * (T / WAVE); i += T) wacc[i] = 0.0;
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
     double lz = 0.0;

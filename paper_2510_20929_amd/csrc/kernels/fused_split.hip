@@ -163,7 +163,7 @@ __global__ __launch_bounds__(T) void split_adjoint_kernel(CallArgs a) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
     __syncthreads();  // the previous item is done with LDS, weights and sums
     if (a.weights && int(threadIdx.x) < a.E) sh.wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
-    if (threadIdx.x < MAX_EIG) sh.wacc[threadIdx.x] = 0.0;
+    for (int i = threadIdx.x; i < MAX_EIG * (T / WAVE); i += T) sh.wacc[i] = 0.0;
     __syncthreads();
     const float* wk = a.weights ? sh.wsh : nullptr;
     float2 o[E];

@@ -207,13 +207,16 @@ __device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m,
     }
   }
   if ((a.want & WANT_WEIGHTS) && wk != nullptr) {
+    // Re <gP, U_e,m>: per-thread sums, then per wave into the wave's own slot of wacc
+    // (no block barrier; the slots are added in a fixed order when the position ends)
+    (void)red;
     for (int e = 0; e < a.E; ++e) {
       const float2* U = a.probe + (size_t(e) * a.M + m) * C::NN;
       double s = 0.0;
 #pragma unroll
       for (int i = 0; i < C::E; ++i) s += double(cdotre(gP[i], U[C::a_pix(t, i)]));
-      s = block_sum<T>(s, red);
-      if (threadIdx.x == 0) wacc[e] += s;
+      s = wave_sum(s);
+      if ((threadIdx.x & (WAVE - 1)) == 0) wacc[e * (T / WAVE) + threadIdx.x / WAVE] += s;
     }
   }
 }
@@ -284,7 +287,11 @@ __device__ __forceinline__ void finish_position(const CallArgs& a, int k, double
   }
   if ((a.want & WANT_WEIGHTS) && a.w_part && a.weights) {
     __syncthreads();
-    if (int(threadIdx.x) < a.E) a.w_part[size_t(k) * a.E + threadIdx.x] = wacc[threadIdx.x];
+    if (int(threadIdx.x) < a.E) {
+      double t = 0.0;
+      for (int w = 0; w < T / WAVE; ++w) t += wacc[threadIdx.x * (T / WAVE) + w];
+      a.w_part[size_t(k) * a.E + threadIdx.x] = t;
+    }
   }
   if (threadIdx.x == 0 && a.wvalid) a.wvalid[k] = 1;
 }
@@ -297,7 +304,7 @@ struct SmallShared {
   float2 tws[N];
   double red[2 * (T / WAVE)];
   float wsh[MAX_EIG];
-  double wacc[MAX_EIG];
+  double wacc[MAX_EIG * (T / WAVE)];  // weight-gradient sums, one slot per eigenprobe and wave
 };
 
 // Workgroup `wg` of `nwg` processes positions wg, wg + nwg, ... of the call `a`.
@@ -365,7 +372,7 @@ __device__ __forceinline__ void small_body(const CallArgs& a, SmallShared<N, T>&
     }
     __syncthreads();
     if (a.weights && int(threadIdx.x) < a.E) wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
-    if (threadIdx.x < MAX_EIG) wacc[threadIdx.x] = 0.0;
+    for (int i = threadIdx.x; i < MAX_EIG * (T / WAVE); i += T) wacc[i] = 0.0;
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
 
@@ -611,7 +618,7 @@ __device__ __forceinline__ void small_body_near(const CallArgs& a, SmallShared<N
     }
     __syncthreads();
     if (a.weights && int(threadIdx.x) < a.E) wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
-    if (threadIdx.x < MAX_EIG) wacc[threadIdx.x] = 0.0;
+    for (int i = threadIdx.x; i < MAX_EIG * (T / WAVE); i += T) wacc[i] = 0.0;
     __syncthreads();
     const float* wk = a.weights ? wsh : nullptr;
     {
