@@ -3,6 +3,8 @@
 // workgroup of 1024 threads per CU whose line blocks fill most of the LDS (512-point
 // lines use the wide line transform, 32 lanes per line); variant 1 runs two workgroups
 // per CU with fewer threads and smaller blocks (512 threads for 256^2, 256 for 512^2).
+#include <algorithm>
+
 #include "big_body.hpp"
 #include "launch.hpp"
 
@@ -58,9 +60,10 @@ __global__ __launch_bounds__(256) void probe_reduce_big_kernel(const float2* __r
 // Eigenprobe gradients from staged probe-wave gradients of a chunk of n positions:
 // part[s][e][m][p] = sum over the positions kk of split s of w[kk][e] gP[kk][m][p]
 // (positions without a valid window are skipped); then the splits are added in order.
+// With one split the sums go straight to the output (added to it when `accumulate`).
 __global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict__ gp, const float* __restrict__ w,
                                                         const int* __restrict__ valid, int n, int E, int M, int NN,
-                                                        int splits, float2* __restrict__ part) {
+                                                        int splits, float2* __restrict__ part, int accumulate) {
   const size_t MN = size_t(M) * NN;
   const int s = blockIdx.y;
   const int per = (n + splits - 1) / splits;
@@ -96,7 +99,10 @@ __global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      if (e < E) part[(size_t(s) * E + e) * MN + g] = acc[e];
+      if (e < E) {
+        float2& o = part[(size_t(s) * E + e) * MN + g];
+        o = accumulate ? cadd(o, acc[e]) : acc[e];
+      }
   }
 }
 
@@ -109,13 +115,21 @@ __global__ void eig_combine_kernel(const float2* __restrict__ part, int splits, 
   }
 }
 
+// Splits run in parallel over position ranges; a chunk of few positions (the minibatch
+// call shapes) takes one split, written straight into the probe gradient.
 hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* valid, int n, int E, int M, int N,
                                    int splits, float2* part, float2* g_probe, int accumulate, hipStream_t st) {
   const size_t MN = size_t(M) * N * N;
   size_t bx = (MN + 255) / 256;
   if (bx > 4096) bx = 4096;
+  splits = std::max(1, std::min(splits, n / 64));
+  if (splits == 1) {
+    hipLaunchKernelGGL(eig_stage_kernel, dim3(unsigned(bx), 1u), dim3(256), 0, st, gp, w, valid, n, E, M, N * N, 1,
+                       g_probe, accumulate);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(eig_stage_kernel, dim3(unsigned(bx), unsigned(splits)), dim3(256), 0, st, gp, w, valid, n, E, M,
-                     N * N, splits, part);
+                     N * N, splits, part, 0);
   const size_t total = size_t(E) * MN;
   size_t b2 = (total + 255) / 256;
   if (b2 > 16384) b2 = 16384;
