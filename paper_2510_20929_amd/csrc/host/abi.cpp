@@ -175,8 +175,7 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
     if ((st = dalloc(p, &p->ipart, size_t(p->fchunk) * G * NN)) != PTYHIP_OK) return st;
     if ((st = dalloc(p, &p->cfr, size_t(p->fchunk) * NN)) != PTYHIP_OK) return st;
     if ((st = dalloc(p, &p->kvalid, size_t(p->fchunk))) != PTYHIP_OK) return st;
-    if (!p->on_chip && (st = dalloc(p, &p->lpart, size_t(p->fchunk) * split_loss_chunks(N))) != PTYHIP_OK)
-      return st;
+    if ((st = dalloc(p, &p->lpart, size_t(p->fchunk) * split_loss_chunks(N))) != PTYHIP_OK) return st;
   }
   if (stage) {
     if ((st = dalloc(p, &p->gpstage, size_t(p->fchunk) * M * NN)) != PTYHIP_OK) return st;
@@ -371,7 +370,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
       c.gwin = want_obj ? p->gwin : nullptr;
       c.wvalid = p->wvalid;
       timing_begin(p, st);
-      hipError_t e = p->on_chip ? launch_fused_split(c, N, p->tune.variant, p->grid, st)
+      hipError_t e = p->on_chip ? launch_fused_split(c, N, p->tune.variant, p->grid, p->lpart, st)
                                 : launch_fused_big_split(c, N, p->tune.variant, p->grid, p->lpart, st);
       timing_end(p, st);
       if (e != hipSuccess) return PTYHIP_EHIP;

@@ -55,7 +55,7 @@ struct Plan {
   float* ipart = nullptr;  // [fchunk][groups][NN]
   float* cfr = nullptr;    // [fchunk][NN]
   int* kvalid = nullptr;   // [fchunk]
-  double* lpart = nullptr; // four-step frames: [fchunk][split_loss_chunks(N)] loss partials
+  double* lpart = nullptr; // [fchunk][split_loss_chunks(N)] loss partials of the mode-split form
   // per-step form
   int chunk = 0;
   float2* obuf = nullptr;

@@ -7,6 +7,7 @@
 
 #include "big_body.hpp"
 #include "launch.hpp"
+#include "split_loss.hpp"
 
 namespace ptyhip {
 
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(T) void split_big_kernel(CallArgs a) {
 // position's partial intensities in group order, the loss against the DC-centred
 // measurement, I_pred, and cfr = 2 dl/dI / (K_norm N^2) (already scaled by gscale); its
 // loss sum goes to lpart[k][c].
-constexpr int SPLIT_LOSS_PIX = 16384;
+constexpr int SPLIT_LOSS_PIX = SPLIT_LOSS_PIX_BIG;
 
 template <int LOSS>
 __global__ __launch_bounds__(1024) void split_loss_nat_kernel(CallArgs a, int N, double* __restrict__ lpart) {
@@ -164,16 +165,34 @@ __global__ __launch_bounds__(1024) void split_loss_nat_kernel(CallArgs a, int N,
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
     double lsum = 0.0;
     if (p.ok) {
+      // PP pixels per thread, their loads in flight together
+      constexpr int PP = SPLIT_LOSS_PIX / 1024;
       const float* ip = a.ipart + size_t(k) * a.groups * NN;
-      for (int pix = p0 + int(threadIdx.x); pix < p1; pix += 1024) {
-        float I = 0.f;
-        for (int g = 0; g < a.groups; ++g) I += ip[size_t(g) * NN + pix];
-        const int ci = centred_index(pix / N, pix % N, N);
+      int px[PP];
+      bool on[PP];
+      float I[PP];
+#pragma unroll
+      for (int j = 0; j < PP; ++j) {
+        px[j] = p0 + int(threadIdx.x) + 1024 * j;
+        on[j] = px[j] < p1;
+        I[j] = 0.f;
+      }
+      for (int g = 0; g < a.groups; ++g) {
+        float v[PP];
+#pragma unroll
+        for (int j = 0; j < PP; ++j) v[j] = on[j] ? ip[size_t(g) * NN + px[j]] : 0.f;
+#pragma unroll
+        for (int j = 0; j < PP; ++j) I[j] += v[j];
+      }
+#pragma unroll
+      for (int j = 0; j < PP; ++j) {
+        if (!on[j]) continue;
+        const int ci = centred_index(px[j] / N, px[j] % N, N);
         float l, cc;
-        loss_terms<LOSS>(I, a.imeas[size_t(k) * NN + ci], a.eps, l, cc);
+        loss_terms<LOSS>(I[j], a.imeas[size_t(k) * NN + ci], a.eps, l, cc);
         lsum += double(l);
-        if (a.ipred) a.ipred[size_t(k) * NN + ci] = I;
-        if (a.cfr) a.cfr[size_t(k) * NN + pix] = a.gscale * cc;
+        if (a.ipred) a.ipred[size_t(k) * NN + ci] = I[j];
+        if (a.cfr) a.cfr[size_t(k) * NN + px[j]] = a.gscale * cc;
       }
     } else if (a.ipred) {
       for (int pix = p0 + int(threadIdx.x); pix < p1; pix += 1024) a.ipred[size_t(k) * NN + pix] = 0.f;
@@ -183,29 +202,14 @@ __global__ __launch_bounds__(1024) void split_loss_nat_kernel(CallArgs a, int N,
   }
 }
 
-// per position: the chunk sums in order, the finiteness check, the validity the adjoint
-// pass reads, and the error latch for positions outside the object or non-finite
+namespace {
 __global__ __launch_bounds__(256) void split_loss_total_kernel(CallArgs a, int N, int nch,
                                                                const double* __restrict__ lpart) {
-  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.K; k += gridDim.x * blockDim.x) {
-    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
-    if (!p.ok) {
-      latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
-      a.loss_part[k] = 0.0;
-      a.kvalid[k] = 0;
-      continue;
-    }
-    double s = 0.0;
-    for (int c = 0; c < nch; ++c) s += lpart[size_t(k) * nch + c];
-    const bool fin = isfinite(s);
-    a.loss_part[k] = fin ? s * double(a.lscale) : 0.0;
-    a.kvalid[k] = fin ? 1 : 0;
-    if (!fin) latch(a.flags, FLAG_NONFINITE);
-  }
+  split_loss_total(a, N, nch, lpart);
 }
+}  // namespace
 
-int split_loss_chunks(int N) { return (N * N + SPLIT_LOSS_PIX - 1) / SPLIT_LOSS_PIX; }
+int split_loss_chunks(int N) { return (N * N + split_loss_pix(N) - 1) / split_loss_pix(N); }
 
 template <int N, int T>
 static hipError_t launch_big_split_t(const CallArgs& a, int grid_items, double* lpart, hipStream_t st) {

@@ -4,11 +4,12 @@
 // groups and every (position, group) pair is a work item of its own, so that a call of
 // K positions keeps K * G workgroups busy instead of K.
 //
-// The incoherent sum couples the groups of a position, hence three launches:
+// The incoherent sum couples the groups of a position, hence three passes:
 //   forward  item (k, g): patch, exit waves and far fields of the group's modes, partial
 //            intensity sum_{m in g} |Psi_k,m|^2 -> ipart[k][g];
-//   loss     position k: I_k = sum_g ipart[k][g] (in group order), loss, dl/dI ->
-//            cfr[k] = 2 dl/dI / (K_norm N^2), validity kvalid[k];
+//   loss     position k, in pixel chunks: I_k = sum_g ipart[k][g] (in group order),
+//            loss, dl/dI -> cfr[k] = 2 dl/dI / (K_norm N^2); then the chunk sums of a
+//            position in order and its validity kvalid[k];
 //   adjoint  item (k, g): far fields recomputed, scaled by cfr[k], transformed back;
 //            the group's patch gradient sum_{m in g} conj(P_m) g_m becomes window k G + g
 //            (the gather adds the G windows of a position), the probe-wave gradients
@@ -21,6 +22,7 @@
 
 #include "launch.hpp"
 #include "small_body.hpp"
+#include "split_loss.hpp"
 
 namespace ptyhip {
 
@@ -72,64 +74,73 @@ __global__ __launch_bounds__(T) void split_forward_kernel(CallArgs a) {
   }
 }
 
+// Loss pass, chunk c of position k (256 threads): element f = i T + t of the frame
+// layout (thread t's element i) for f in [c SPLIT_LOSS_PIX_SMALL, (c + 1) ...): I = the
+// sum of the position's partial intensities in group order, the loss against the
+// measurement at the element's centred pixel, I_pred there, cfr = 2 dl/dI / (K_norm N^2)
+// in the frame layout; the chunk's loss sum goes to lpart[k][c]. Chunks keep many
+// workgroups busy when a call has few positions.
 template <int N, int T, int LOSS>
-__global__ __launch_bounds__(T) void split_loss_kernel(CallArgs a) {
+__global__ __launch_bounds__(256) void split_loss_chunk_kernel(CallArgs a, double* __restrict__ lpart) {
   using C = SmallCtx<N, T>;
-  constexpr int E = C::E;
-  __shared__ double red[2 * (T / WAVE)];
+  __shared__ double red[2 * (256 / WAVE)];
+  constexpr int NN = C::NN;
+  const int c = blockIdx.x, nch = gridDim.x;
+  const int f0 = c * SPLIT_LOSS_PIX_SMALL, f1 = min(NN, f0 + SPLIT_LOSS_PIX_SMALL);
   const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
-  for (int k = blockIdx.x; k < a.K; k += gridDim.x) {
+  constexpr int PP = SPLIT_LOSS_PIX_SMALL / 256;  // elements per thread, their loads in flight together
+  for (int k = blockIdx.y; k < a.K; k += gridDim.y) {
     const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
-    if (!p.ok) {
-      if (threadIdx.x == 0) {
-        latch(a.flags, p.finite ? FLAG_BOUNDS : FLAG_NONFINITE);
-        a.loss_part[k] = 0.0;
-        a.kvalid[k] = 0;
-      }
-      if (a.ipred)
-        for (int i = threadIdx.x; i < C::NN; i += T) a.ipred[size_t(k) * C::NN + i] = 0.f;
-      continue;
-    }
-    const int t = opaque_tid();
-    float I[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) I[i] = 0.f;
-    for (int g = 0; g < a.groups; ++g) {
-      const float* src = a.ipart + (size_t(k) * a.groups + g) * C::NN;
-#pragma unroll
-      for (int i = 0; i < E; ++i) I[i] += src[size_t(i) * T + t];
-    }
-    const float* im = a.imeas + size_t(k) * C::NN;
-    float imv[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) imv[i] = __builtin_nontemporal_load(im + C::d_centred(t, i));
-    if (a.ipred) {
-      float* ip = a.ipred + size_t(k) * C::NN;
-#pragma unroll
-      for (int i = 0; i < E; ++i) __builtin_nontemporal_store(I[i], ip + C::d_centred(t, i));
-    }
+    const float* ip = a.ipart + size_t(k) * a.groups * NN;
     double lsum = 0.0;
+    int fj[PP], cj[PP];
+    bool on[PP];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      float l, c;
-      loss_terms<LOSS>(I[i], imv[i], a.eps, l, c);
-      lsum += double(l);
-      I[i] = c;
+    for (int j = 0; j < PP; ++j) {
+      fj[j] = f0 + int(threadIdx.x) + 256 * j;
+      on[j] = fj[j] < f1;
+      cj[j] = on[j] ? C::d_centred(fj[j] % T, fj[j] / T) : 0;
     }
-    const double tot = block_sum<T>(lsum, red);
-    const bool fin = isfinite(tot);
-    if (threadIdx.x == 0) {
-      a.loss_part[k] = fin ? tot * double(a.lscale) : 0.0;
-      a.kvalid[k] = fin ? 1 : 0;
-      if (!fin) latch(a.flags, FLAG_NONFINITE);
-    }
-    if (fin && a.cfr) {
-      float* cd = a.cfr + size_t(k) * C::NN;
+    if (!p.ok) {
+      if (a.ipred)
 #pragma unroll
-      for (int i = 0; i < E; ++i) cd[size_t(i) * T + t] = a.gscale * I[i];
+        for (int j = 0; j < PP; ++j)
+          if (on[j]) a.ipred[size_t(k) * NN + cj[j]] = 0.f;
+    } else {
+      float I[PP], im[PP];
+#pragma unroll
+      for (int j = 0; j < PP; ++j) {
+        I[j] = 0.f;
+        im[j] = on[j] ? a.imeas[size_t(k) * NN + cj[j]] : 0.f;
+      }
+      for (int g = 0; g < a.groups; ++g) {
+        float v[PP];
+#pragma unroll
+        for (int j = 0; j < PP; ++j) v[j] = on[j] ? ip[size_t(g) * NN + fj[j]] : 0.f;
+#pragma unroll
+        for (int j = 0; j < PP; ++j) I[j] += v[j];
+      }
+#pragma unroll
+      for (int j = 0; j < PP; ++j) {
+        if (!on[j]) continue;
+        float l, cc;
+        loss_terms<LOSS>(I[j], im[j], a.eps, l, cc);
+        lsum += double(l);
+        if (a.ipred) a.ipred[size_t(k) * NN + cj[j]] = I[j];
+        if (a.cfr) a.cfr[size_t(k) * NN + fj[j]] = a.gscale * cc;
+      }
     }
+    const double tot = block_sum<256>(lsum, red);
+    if (threadIdx.x == 0) lpart[size_t(k) * nch + c] = tot;
   }
 }
+
+namespace {
+__global__ __launch_bounds__(256) void split_loss_total_small_kernel(CallArgs a, int N, int nch,
+                                                                     const double* __restrict__ lpart) {
+  split_loss_total(a, N, nch, lpart);
+}
+}  // namespace
 
 // Scratch per workgroup: one frame, the running patch gradient of a group of several modes.
 template <int N, int T>
@@ -226,29 +237,32 @@ __global__ __launch_bounds__(T) void split_adjoint_kernel(CallArgs a) {
 }
 
 template <int N, int T>
-static hipError_t launch_split_t(const CallArgs& a, int grid, int items_grid, hipStream_t st) {
+static hipError_t launch_split_t(const CallArgs& a, int items_grid, double* lpart, hipStream_t st) {
   hipLaunchKernelGGL((split_forward_kernel<N, T>), dim3(items_grid), dim3(T), 0, st, a);
-  if (a.loss == 0) hipLaunchKernelGGL((split_loss_kernel<N, T, 0>), dim3(grid), dim3(T), 0, st, a);
-  else hipLaunchKernelGGL((split_loss_kernel<N, T, 1>), dim3(grid), dim3(T), 0, st, a);
+  const int nch = split_loss_chunks(N);
+  const dim3 lg(unsigned(nch), unsigned(a.K < 65535 ? a.K : 65535));
+  if (a.loss == 0) hipLaunchKernelGGL((split_loss_chunk_kernel<N, T, 0>), lg, dim3(256), 0, st, a, lpart);
+  else hipLaunchKernelGGL((split_loss_chunk_kernel<N, T, 1>), lg, dim3(256), 0, st, a, lpart);
+  hipLaunchKernelGGL(split_loss_total_small_kernel, dim3(unsigned((a.K + 255) / 256)), dim3(256), 0, st, a, N, nch,
+                     (const double*)lpart);
   if (a.mode == MODE_FWD_ADJ) hipLaunchKernelGGL((split_adjoint_kernel<N, T>), dim3(items_grid), dim3(T), 0, st, a);
   return hipGetLastError();
 }
 
-// The three launches of one chunk of positions; `grid` bounds the workgroups of each
-// launch (at most one per position for the loss, one per item for the others).
-hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, hipStream_t st) {
+// The passes of one chunk of positions; `grid` bounds the workgroups of the forward and
+// adjoint passes (at most one per item); lpart: [K][split_loss_chunks(N)] loss partials.
+hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, double* lpart, hipStream_t st) {
   if (a.K <= 0) return hipSuccess;
   const int items = a.K * a.groups;
   const int g_items = std::max(1, std::min(grid, items));
-  const int g_pos = std::max(1, std::min(grid, a.K));
   const int T = fused_small_threads(N, variant);
   switch (N) {
-    case 16: return launch_split_t<16, 64>(a, g_pos, g_items, st);
-    case 32: return launch_split_t<32, 128>(a, g_pos, g_items, st);
-    case 64: return T == 256 ? launch_split_t<64, 256>(a, g_pos, g_items, st)
-                             : launch_split_t<64, 512>(a, g_pos, g_items, st);
-    case 128: return T == 1024 ? launch_split_t<128, 1024>(a, g_pos, g_items, st)
-                               : launch_split_t<128, 512>(a, g_pos, g_items, st);
+    case 16: return launch_split_t<16, 64>(a, g_items, lpart, st);
+    case 32: return launch_split_t<32, 128>(a, g_items, lpart, st);
+    case 64: return T == 256 ? launch_split_t<64, 256>(a, g_items, lpart, st)
+                             : launch_split_t<64, 512>(a, g_items, lpart, st);
+    case 128: return T == 1024 ? launch_split_t<128, 1024>(a, g_items, lpart, st)
+                               : launch_split_t<128, 512>(a, g_items, lpart, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -22,7 +22,8 @@ template <> __device__ __forceinline__ float2 vzero<float2>() { return make_floa
 // Positions are taken in chunks: every thread tests a few positions for overlap with the
 // tile, the hits are compacted in position order (wave ballots + a block prefix, so the
 // order never depends on timing), and then each thread adds the window values of the
-// hits at its 4 pixels, issuing the loads of 4 hits before adding them in order.
+// hits at its pixels, issuing the loads of several hits (8 with one pixel per thread,
+// 4 with four) before adding them in order.
 // `win` holds [K][S][N+1][N+1] windows of value type V (float2 gradients, float
 // illumination), `out` the [S][H][W] result.
 // `rep` windows share one position (window k belongs to position k / rep; the mode-split
@@ -38,6 +39,7 @@ __device__ __forceinline__ void gather_tile_at(const V* __restrict__ win, const 
   __shared__ int wcnt[NT / 64];
   constexpr int RPP = NT / TS;  // rows per pass
   constexpr int PJ = TS / RPP;   // passes (pixels per thread)
+  constexpr int HB = PJ == 1 ? 8 : 4;  // hits whose loads are in flight together
   static_assert(RPP * TS == NT && PJ * RPP == TS, "the tile must split evenly over the threads");
   const int WN = N + 1;
   const int tx0 = bx * TS, ty0 = by * TS, s = bz;
@@ -82,10 +84,10 @@ __device__ __forceinline__ void gather_tile_at(const V* __restrict__ win, const 
       nh += tot;
       __syncthreads();  // wcnt is rewritten by the next round; the hits are visible
     }
-    for (int h = 0; h < nh; h += 4) {
-      V t[4][PJ];
+    for (int h = 0; h < nh; h += HB) {
+      V t[HB][PJ];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < HB; ++u) {
         const bool on = h + u < nh;
         const int hh = on ? h + u : nh - 1;  // in-range LDS slot also for the unused tail
         const int y0 = hy[hh], px = on ? x - hx[hh] : -1;
@@ -97,7 +99,7 @@ __device__ __forceinline__ void gather_tile_at(const V* __restrict__ win, const 
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < HB; ++u)
 #pragma unroll
         for (int j = 0; j < PJ; ++j) acc[j] = vadd(acc[j], t[u][j]);
     }

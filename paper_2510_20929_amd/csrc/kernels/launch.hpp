@@ -84,7 +84,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
                                  bool near = false, bool fshift = false);
 hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
 hipError_t launch_fused_small_fs(const CallArgs& a, int N, int threads, int grid, hipStream_t st);
-hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, hipStream_t st);
+hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, double* lpart, hipStream_t st);
 hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int grid, float2* g_probe,
                                      int accumulate, hipStream_t st);
 
