@@ -377,6 +377,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
       if (a.mode != MODE_FWD_ADJ) continue;
       const bool add = acc || k0 > 0;
       if (want_obj) {
+        if (launch_window_group_sum(p->gwin, p->wvalid, n, G, N, st) != hipSuccess) return PTYHIP_EHIP;
         GatherArgs g{};
         g.gwin = p->gwin;
         g.wvalid = p->wvalid;

@@ -6,16 +6,27 @@
 
 namespace ptyhip {
 
-__global__ __launch_bounds__(1024) void loss_reduce_kernel(const double* __restrict__ part, int K, double* out,
-                                                           int accumulate) {
-  __shared__ double red[1024 / WAVE];
+// Everything in one launch: workgroup 0 also reduces the loss and dL/d(lambda z) (a
+// deterministic FP64 tree over the per-position sums), every workgroup takes a
+// grid-stride share of the elementwise outputs.
+__device__ __forceinline__ double position_sum(const double* __restrict__ part, int K, double* red) {
   double s = 0.0;
-  for (int k = threadIdx.x; k < K; k += 1024) s += part[k];
-  s = block_sum<1024>(s, red);
-  if (threadIdx.x == 0) *out = accumulate ? (*out + s) : s;
+  for (int k = threadIdx.x; k < K; k += 256) s += part[k];
+  return block_sum<256>(s, red);
 }
 
-__global__ void finalize_elems_kernel(FinalArgs f) {
+__global__ __launch_bounds__(256) void finalize_elems_kernel(FinalArgs f) {
+  __shared__ double red[256 / WAVE];
+  if (blockIdx.x == 0) {
+    if (f.loss) {
+      const double s = position_sum(f.loss_part, f.K, red);
+      if (threadIdx.x == 0) *f.loss = f.accumulate ? (*f.loss + s) : s;
+    }
+    if (f.g_lz && f.lz_part) {
+      const double s = position_sum(f.lz_part, f.K, red);
+      if (threadIdx.x == 0) *f.g_lz = f.accumulate ? (*f.g_lz + s) : s;
+    }
+  }
   const size_t tid = size_t(blockIdx.x) * blockDim.x + threadIdx.x, stride = size_t(gridDim.x) * blockDim.x;
   // with rep > 1 every position has rep partial sums (one per mode group), added in order
   const int rep = f.rep > 1 ? f.rep : 1;
@@ -43,18 +54,15 @@ __global__ void finalize_elems_kernel(FinalArgs f) {
 }
 
 hipError_t launch_finalize(const FinalArgs& f, hipStream_t st) {
-  if (f.loss) hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, f.loss_part, f.K, f.loss, f.accumulate);
-  if (f.g_lz && f.lz_part)
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, f.lz_part, f.K, f.g_lz, f.accumulate);
   size_t n = 0;
   if (f.g_pos) n = size_t(f.K) * 2;
   if (f.g_w && size_t(f.K) * f.E > n) n = size_t(f.K) * f.E;
   if (f.g_probe && f.probe_elems > n) n = f.probe_elems;
-  if (n > 0) {
-    size_t blocks = (n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(finalize_elems_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, f);
-  }
+  if (n == 0 && !f.loss && !(f.g_lz && f.lz_part)) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(finalize_elems_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, f);
   return hipGetLastError();
 }
 

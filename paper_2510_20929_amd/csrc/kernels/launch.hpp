@@ -76,6 +76,8 @@ inline int gather_tile_side(int H, int W, int S) {
 
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st);
 hipError_t launch_window_gather(const GatherArgs& g, hipStream_t st);
+// mode-split form: add the G group windows of each of npos positions into its first
+hipError_t launch_window_group_sum(float2* gwin, int* wvalid, int npos, int G, int N, hipStream_t st);
 hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inverse, hipStream_t st);
 hipError_t run_plain_chunk(PlainArgs b, hipStream_t st);
 
