@@ -303,8 +303,10 @@ ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
  * routine. Positions are processed in chunks that fit the array, with as many
  * persistent workgroups as fit beside them (at most one per CU, or tune->grid).
  *   desc, tune   problem and implementation choice as for ptyhip_plan_create_ex (tune
- *                may be NULL); N <= 128, one slice, far field (bilinear or Fourier-shift
- *                patch), else PTYHIP_EUNSUPPORTED
+ *                may be NULL; its mode_groups and probe_stage fields are ignored: a
+ *                workgroup always takes whole positions and accumulates the probe
+ *                gradient in its own frames); N <= 128, one slice, far field (bilinear or
+ *                Fourier-shift patch), else PTYHIP_EUNSUPPORTED
  *   other args   as ptyhip_forward_adjoint (device pointers owned by the caller);
  *                PTYHIP_PLAIN is EUNSUPPORTED, PTYHIP_GRAD_LAMBDA_Z is EINVAL
  *   err_flags    device uint32[1] or NULL: receives this call's error latch
