@@ -399,10 +399,10 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           // LDS slot)
           probe_batch(m, rb, b0, P, [&](int e, const float2(&u)[BAT]) {
             if (!want_w) return;
-            double t = 0.0;
+            float tf = 0.f;  // the batch's terms in FP32, the wave and position sums in FP64
 #pragma unroll
-            for (int j = 0; j < BAT; ++j) t += double(cdotre(gP[j], u[j]));
-            t = wave_sum(t);
+            for (int j = 0; j < BAT; ++j) tf += cdotre(gP[j], u[j]);
+            const double t = wave_sum(double(tf));
             if (lane == 0) sh.wred[e * NW + wave] += t;
           });
           float2 gprev[BAT];
@@ -438,6 +438,7 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
           const float2* prev = sh.prevg[rb & 1];
           const float2 z = make_float2(0.f, 0.f);
           const int rows = RB + (rb == NB - 1 ? 1 : 0);
+          float fy = 0.f, fx = 0.f;  // the block's few terms per thread in FP32, then FP64
           for (int idx = tid; idx < rows * WN; idx += T) {
             const int ry = idx / WN, px = idx - ry * WN, py = rb * RB + ry;
             const bool iy0 = py < N, iy1 = py >= 1, ix0 = px < N, ix1 = px >= 1;
@@ -460,10 +461,12 @@ __device__ __forceinline__ void big_body(const CallArgs& a, BigShared<N, TT>& sh
               hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
               hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
               hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
-              gy += double(cdotre(hy, A));
-              gx += double(cdotre(hx, A));
+              fy += cdotre(hy, A);
+              fx += cdotre(hx, A);
             }
           }
+          gy += double(fy);
+          gx += double(fx);
           for (int x = tid; x < N; x += T) sh.prevg[(rb + 1) & 1][x] = tile[(RB - 1) * RP + x];
         }
         __syncthreads();

@@ -212,10 +212,10 @@ __device__ __forceinline__ void probe_gradients(const CallArgs& a, int k, int m,
     (void)red;
     for (int e = 0; e < a.E; ++e) {
       const float2* U = a.probe + (size_t(e) * a.M + m) * C::NN;
-      double s = 0.0;
+      float sf = 0.f;  // the thread's few terms in FP32, the wave and position sums in FP64
 #pragma unroll
-      for (int i = 0; i < C::E; ++i) s += double(cdotre(gP[i], U[C::a_pix(t, i)]));
-      s = wave_sum(s);
+      for (int i = 0; i < C::E; ++i) sf += cdotre(gP[i], U[C::a_pix(t, i)]);
+      const double s = wave_sum(double(sf));
       if ((threadIdx.x & (WAVE - 1)) == 0) wacc[e * (T / WAVE) + threadIdx.x / WAVE] += s;
     }
   }
@@ -236,6 +236,7 @@ __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p,
   const float2 z = make_float2(0.f, 0.f);
   auto body = [&](auto obj_c, auto pos_c) {
     constexpr bool OBJ = decltype(obj_c)::value, POS = decltype(pos_c)::value;
+    float fy = 0.f, fx = 0.f;  // the thread's (N+1)^2 / T terms in FP32, then FP64
 #pragma unroll 4
     for (int idx = threadIdx.x; idx < WN * WN; idx += T) {
       const int py = idx / WN, px = idx - py * WN;
@@ -259,9 +260,13 @@ __device__ __forceinline__ void window_pass(const CallArgs& a, const PosInfo& p,
         hy.y = (1.f - p.fx) * (g10.y - g00.y) + p.fx * (g11.y - g01.y);
         hx.x = (1.f - p.fy) * (g01.x - g00.x) + p.fy * (g11.x - g10.x);
         hx.y = (1.f - p.fy) * (g01.y - g00.y) + p.fy * (g11.y - g10.y);
-        gy += double(cdotre(hy, A));
-        gx += double(cdotre(hx, A));
+        fy += cdotre(hy, A);
+        fx += cdotre(hx, A);
       }
+    }
+    if constexpr (POS) {
+      gy += double(fy);
+      gx += double(fx);
     }
   };
   using T0 = std::false_type;
