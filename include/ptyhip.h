@@ -111,7 +111,9 @@ typedef struct {
   float lambda_z;       /* slice spacing times wavelength, px^2 (used when S > 1) */
   double norm_count;    /* K_norm of the 1/(K_norm N^2) normaliser; <= 0: K of the call */
   int32_t propagation;  /* a ptyhip_propagation value: far- or near-field propagation in the
-                           forward model (Software design, Overview); near needs S == 1, N <= 128 */
+                           forward model (Software design, Overview); near needs S == 1; near
+                           fields of 256^2 and 512^2 frames run the per-step form (no
+                           PTYHIP_GRAD_LAMBDA_Z there) */
   float det_lambda_z;   /* near field: wavelength times detector distance, px^2; the detector
                            wave is F^-1(exp(-i pi det_lambda_z (fy^2 + fx^2)) F chi) */
   int32_t subpixel;     /* a ptyhip_subpixel value: bilinear interpolation (default) or the
@@ -210,7 +212,8 @@ ptyhip_status ptyhip_forward_adjoint(ptyhip_plan plan, void* stream, int32_t K, 
  *     dL/dlz = sum_k,m sum_{s>0} Re sum_f conj(F g_psi_s) (-i pi q^2) F psi_s, with
  *     psi_s the incident wave of slice s and g_psi_s its gradient.
  * The flag with a single-slice far-field plan, or with a NULL g_lambda_z, is EINVAL;
- * with PTYHIP_PLAIN it is EUNSUPPORTED (the fused kernels compute it). */
+ * with PTYHIP_PLAIN, or with a near-field plan of frames above 128^2 (which runs the
+ * per-step form), it is EUNSUPPORTED (the fused kernels compute it). */
 ptyhip_status ptyhip_forward_adjoint_ex(ptyhip_plan plan, void* stream, int32_t K, uint32_t flags, const float* obj,
                                         const float* probe, const float* weights, const float* positions,
                                         const float* I_meas, double* loss, float* I_pred, float* g_obj,

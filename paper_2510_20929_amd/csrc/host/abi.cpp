@@ -139,7 +139,9 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   } else {
     p->threads = fused_big_threads(N, p->tune.variant);
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
-    p->big_fused_ready = S == 1;
+    // the four-step kernel models the far field; near-field plans of these frame sizes
+    // run the per-step form
+    p->big_fused_ready = S == 1 && d.propagation == PTYHIP_PROP_FAR;
   }
   // persistent grid: one workgroup per CU (the on-chip frame or the line blocks of the
   // four-step transforms fill most of a CU's LDS), two for the four-step layout with
@@ -229,7 +231,7 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
   if (d->propagation != PTYHIP_PROP_FAR && d->propagation != PTYHIP_PROP_NEAR) return PTYHIP_EINVAL;
   if (d->propagation == PTYHIP_PROP_NEAR) {
     if (!std::isfinite(d->det_lambda_z)) return PTYHIP_ENONFINITE;
-    if (d->n_slices > 1 || d->frame > 128) return PTYHIP_EUNSUPPORTED;
+    if (d->n_slices > 1) return PTYHIP_EUNSUPPORTED;
   }
   if (d->subpixel != PTYHIP_SUBPIXEL_BILINEAR && d->subpixel != PTYHIP_SUBPIXEL_FOURIER) return PTYHIP_EINVAL;
   if (d->subpixel == PTYHIP_SUBPIXEL_FOURIER &&
@@ -523,7 +525,7 @@ static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uin
   // lambda z of the plan's propagator: the detector distance (near field) or the slice
   // spacing (several slices); a single-slice far-field plan has none
   if (want_lz && (!(near || d.n_slices > 1) || !g_lz)) return PTYHIP_EINVAL;
-  if ((near || d.subpixel == PTYHIP_SUBPIXEL_FOURIER) && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
+  if (d.subpixel == PTYHIP_SUBPIXEL_FOURIER && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_lz && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;
@@ -535,6 +537,7 @@ static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uin
   const int mode = (forward_only || !any_grad) ? MODE_FORWARD : MODE_FWD_ADJ;
   const bool plain = (flags & PTYHIP_PLAIN) != 0;
   const bool fused = uses_fused(p, plain);
+  if (want_lz && !fused) return PTYHIP_EUNSUPPORTED;  // the fused kernels compute dL/dlz
   CallArgs a = make_args(p, K, mode, fused, obj, probe, weights, positions, I_meas, nullptr, nullptr, I_pred,
                          want_obj ? g_obj : nullptr, want_probe, want_pos, want_w);
   if (want_lz) {

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void pl_loss_kernel(PlainArgs b) {
   for (int px = threadIdx.x; px < NN; px += 256) {
     float I = 0.f;
     for (int m = 0; m < a.M; ++m) I += cabs2(b.xbuf[(size_t(c) * a.M + m) * NN + px]);
-    const int ci = centred_index(px / N, px % N, N);
+    const int ci = a.near ? px : centred_index(px / N, px % N, N);  // near field: natural order
     float l = 0.f, cf = 0.f;
     if (ok) loss_terms<LOSS>(I, a.imeas[size_t(k) * NN + ci], a.eps, l, cf);
     if (a.ipred) a.ipred[size_t(k) * NN + ci] = ok ? I : 0.f;
@@ -388,6 +388,12 @@ hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
         hipLaunchKernelGGL(pl_copy_kernel, dim3(4096), blk, 0, st, dst, (const float2*)b.xbuf, size_t(C) * M * fr);
       }
     }
+    if (a.near) {
+      // near field: Fresnel propagation to the detector, F^-1 H F (the far field above is F)
+      if (a.mode == MODE_APPLY_A) return hipErrorNotSupported;
+      hipLaunchKernelGGL(pl_tf_kernel, pix_grid(NN, C * M), blk, 0, st, b.xbuf, a.tfd, NN, 0);
+      if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, true, st)) != hipSuccess) return err;
+    }
     if (a.mode == MODE_APPLY_A) {
       hipLaunchKernelGGL(pl_store_psi_kernel, pix_grid(NN, C * M), blk, 0, st, b);
       return hipGetLastError();
@@ -396,7 +402,13 @@ hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
     else hipLaunchKernelGGL(pl_loss_kernel<1>, dim3(C), blk, 0, st, b);
     if (a.mode == MODE_FORWARD) return hipGetLastError();
     hipLaunchKernelGGL(pl_residual_kernel, pix_grid(NN, C * M), blk, 0, st, b);
+    if (a.near) {
+      // adjoint of F^-1 H F: F^-1 conj(H) F; its final F^-1 is the one below
+      if ((err = launch_fft2(b.xbuf, C * M, N, a.tw, false, st)) != hipSuccess) return err;
+      hipLaunchKernelGGL(pl_tf_kernel, pix_grid(NN, C * M), blk, 0, st, b.xbuf, a.tfd, NN, 1);
+    }
   } else {
+    if (a.near) return hipErrorNotSupported;  // the linear maps are far field only
     if (S > 1) return hipErrorNotSupported;  // multislice apply_AH needs the fused path
     hipLaunchKernelGGL(pl_loady_kernel, pix_grid(NN, C * M), blk, 0, st, b);
   }
