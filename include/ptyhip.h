@@ -117,8 +117,9 @@ typedef struct {
   float det_lambda_z;   /* near field: wavelength times detector distance, px^2; the detector
                            wave is F^-1(exp(-i pi det_lambda_z (fy^2 + fx^2)) F chi) */
   int32_t subpixel;     /* a ptyhip_subpixel value: bilinear interpolation (default) or the
-                           Fourier shift of the integer N x N window; Fourier needs S == 1,
-                           N <= 128 and the far field */
+                           Fourier shift of the integer N x N window; Fourier needs S == 1
+                           and the far field; Fourier-shift plans of 256^2 and 512^2 frames
+                           run the per-step form */
 } ptyhip_desc;
 
 /* Optional implementation choices (the autotuner's search space). Zero = default. */

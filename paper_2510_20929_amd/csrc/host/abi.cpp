@@ -139,9 +139,9 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   } else {
     p->threads = fused_big_threads(N, p->tune.variant);
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
-    // the four-step kernel models the far field; near-field plans of these frame sizes
-    // run the per-step form
-    p->big_fused_ready = S == 1 && d.propagation == PTYHIP_PROP_FAR;
+    // the four-step kernel models the far field with the bilinear patch; near-field and
+    // Fourier-shift plans of these frame sizes run the per-step form
+    p->big_fused_ready = S == 1 && d.propagation == PTYHIP_PROP_FAR && d.subpixel == PTYHIP_SUBPIXEL_BILINEAR;
   }
   // persistent grid: one workgroup per CU (the on-chip frame or the line blocks of the
   // four-step transforms fill most of a CU's LDS), two for the four-step layout with
@@ -201,6 +201,7 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   if ((st = dalloc(p, &p->gbuf, size_t(S) * C * NN)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->cbuf, C * NN)) != PTYHIP_OK) return st;
   if ((st = dalloc(p, &p->valid, C)) != PTYHIP_OK) return st;
+  if (d.subpixel == PTYHIP_SUBPIXEL_FOURIER && (st = dalloc(p, &p->fsbuf, C * NN)) != PTYHIP_OK) return st;
   p->plain_bytes = p->bytes - before;
 
   // illumination map / normalised gradients
@@ -234,8 +235,7 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
     if (d->n_slices > 1) return PTYHIP_EUNSUPPORTED;
   }
   if (d->subpixel != PTYHIP_SUBPIXEL_BILINEAR && d->subpixel != PTYHIP_SUBPIXEL_FOURIER) return PTYHIP_EINVAL;
-  if (d->subpixel == PTYHIP_SUBPIXEL_FOURIER &&
-      (d->n_slices > 1 || d->frame > 128 || d->propagation != PTYHIP_PROP_FAR))
+  if (d->subpixel == PTYHIP_SUBPIXEL_FOURIER && (d->n_slices > 1 || d->propagation != PTYHIP_PROP_FAR))
     return PTYHIP_EUNSUPPORTED;
   return PTYHIP_OK;
 }
@@ -342,6 +342,7 @@ static ptyhip_status run_call(Plan* p, const CallArgs& a, bool plain, bool acc, 
       b.gbuf = p->gbuf;
       b.cbuf = p->cbuf;
       b.valid = p->valid;
+      b.fsbuf = p->fsbuf;
       hipError_t e = run_plain_chunk(b, st);
       if (e == hipErrorNotSupported) return PTYHIP_EUNSUPPORTED;
       if (e != hipSuccess) return PTYHIP_EHIP;
@@ -525,7 +526,6 @@ static ptyhip_status enqueue_forward_adjoint(Plan* p, hipStream_t st, int K, uin
   // lambda z of the plan's propagator: the detector distance (near field) or the slice
   // spacing (several slices); a single-slice far-field plan has none
   if (want_lz && (!(near || d.n_slices > 1) || !g_lz)) return PTYHIP_EINVAL;
-  if (d.subpixel == PTYHIP_SUBPIXEL_FOURIER && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_lz && (flags & PTYHIP_PLAIN)) return PTYHIP_EUNSUPPORTED;
   if (want_obj && !g_obj) return PTYHIP_EINVAL;
   if (want_probe && !g_probe) return PTYHIP_EINVAL;

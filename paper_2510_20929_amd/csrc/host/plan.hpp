@@ -65,6 +65,7 @@ struct Plan {
   float2* gbuf = nullptr;
   float* cbuf = nullptr;
   int* valid = nullptr;
+  float2* fsbuf = nullptr;  // Fourier-shift patch, per-step form: shifted window spectra [chunk][NN]
   size_t plain_bytes = 0;
   // illumination map and normalised gradients
   float* illum_g = nullptr;   // [E(E+1)/2][N][N] probe Gram terms

@@ -17,6 +17,7 @@ struct PlainArgs {
   float2* gbuf;    // [S][C][N*N]   patch gradients
   float* cbuf;     // [C][N*N]      dl/dI
   int* valid;      // [C]
+  float2* fsbuf;   // [C][N*N]      Fourier-shift patch: shifted window spectrum S F w, or nullptr
 };
 
 // Final reductions of one call.

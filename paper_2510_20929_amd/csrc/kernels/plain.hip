@@ -124,7 +124,8 @@ hipError_t launch_fft2(float2* X, int nframes, int N, const float2* tw, bool inv
 __global__ void pl_gather_kernel(PlainArgs b) {
   const CallArgs& a = b.a;
   const int c = blockIdx.y, k = b.k0 + c, NN = b.N * b.N;
-  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  // the Fourier-shift patch keeps the bilinear window rule without the position-gradient margin
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && !a.fshift;
   const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, want_pos);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     b.valid[c] = p.ok ? 1 : 0;
@@ -135,8 +136,71 @@ __global__ void pl_gather_kernel(PlainArgs b) {
   const int y = px / b.N, x = px % b.N;
   for (int s = 0; s < a.S; ++s) {
     float2 v = make_float2(0.f, 0.f);
-    if (p.ok) v = bilinear(a.obj + size_t(s) * a.H * a.W, a.W, p, y, x);
+    if (p.ok)
+      v = a.fshift ? a.obj[size_t(p.y0 + y) * a.W + (p.x0 + x)]   // integer window, shifted below
+                   : bilinear(a.obj + size_t(s) * a.H * a.W, a.W, p, y, x);
     b.obuf[(size_t(s) * b.C + c) * NN + px] = v;
+  }
+}
+
+// Fourier-shift patch: the phase exp(i (cy fy + cx fx)) of frequency pixel px (natural
+// order; cy, cx = 2 pi times the signed frequency index / N) for the position's fraction
+__device__ __forceinline__ float2 fs_phase(const PosInfo& p, int px, int N, float& cy, float& cx) {
+  const int ky = px / N, kx = px % N;
+  cy = 6.283185307179586f * float(ky < N / 2 ? ky : ky - N) / float(N);
+  cx = 6.283185307179586f * float(kx < N / 2 ? kx : kx - N) / float(N);
+  float sn, cs;
+  sincosf(cy * p.fy + cx * p.fx, &sn, &cs);
+  return make_float2(cs, sn);
+}
+
+// X = F w in obuf: X *= S (conj(S) with `adjoint`, in gbuf); the shifted spectrum S X is
+// kept in fsbuf for the position gradient
+__global__ void pl_fs_shift_kernel(PlainArgs b, int adjoint) {
+  const CallArgs& a = b.a;
+  const int NN = b.N * b.N;
+  const int c = blockIdx.y, k = b.k0 + c;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= NN) return;
+  const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, false);
+  float cy, cx;
+  const float2 sh = fs_phase(p, px, b.N, cy, cx);
+  if (adjoint) {
+    float2& g = b.gbuf[size_t(c) * NN + px];
+    g = cmulc(sh, g);
+  } else {
+    float2& x = b.obuf[size_t(c) * NN + px];
+    x = cmul(x, sh);
+    if (b.fsbuf) b.fsbuf[size_t(c) * NN + px] = x;
+  }
+}
+
+// Fourier-shift position gradient (one block per position): with G = F g_o and Z = S X,
+// dL/d(fy, fx) = sum_px (cy, cx) Re(i conj(G) Z)
+__global__ __launch_bounds__(256) void pl_fs_posgrad_kernel(PlainArgs b) {
+  const CallArgs& a = b.a;
+  __shared__ double red[2 * (256 / WAVE)];
+  const int NN = b.N * b.N;
+  const int c = blockIdx.x, k = b.k0 + c;
+  double v[2] = {0.0, 0.0};
+  if (b.valid[c]) {
+    const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, false);
+    float fy = 0.f, fx = 0.f;
+    for (int px = threadIdx.x; px < NN; px += 256) {
+      float cy, cx;
+      (void)fs_phase(p, px, b.N, cy, cx);
+      const float2 G = b.gbuf[size_t(c) * NN + px], Z = b.fsbuf[size_t(c) * NN + px];
+      const float q = G.y * Z.x - G.x * Z.y;
+      fy += cy * q;
+      fx += cx * q;
+    }
+    v[0] = double(fy);
+    v[1] = double(fx);
+  }
+  block_sum_n<256, 2>(v, red);
+  if (threadIdx.x == 0) {
+    a.pos_part[2 * k] = v[0];
+    a.pos_part[2 * k + 1] = v[1];
   }
 }
 
@@ -296,11 +360,15 @@ __global__ void pl_scatter_kernel(PlainArgs b, int s) {
   const int c = blockIdx.y, k = b.k0 + c;
   const int px = blockIdx.x * blockDim.x + threadIdx.x;
   if (px >= NN || !b.valid[c]) return;
-  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && !a.fshift;
   const PosInfo p = parse_position(a.pos, k, b.N, a.H, a.W, want_pos);
   const float2 g = b.gbuf[(size_t(s) * b.C + c) * NN + px];
   const int y = px / b.N, x = px % b.N;
   float2* base = a.gobj + size_t(s) * a.H * a.W + size_t(p.y0 + y) * a.W + (p.x0 + x);
+  if (a.fshift) {  // window gradient of the Fourier-shift patch: the integer window
+    atomic_add_c(base, g);
+    return;
+  }
   atomic_add_c(base, cscale(g, (1.f - p.fy) * (1.f - p.fx)));
   if (p.fx > 0.f) atomic_add_c(base + 1, cscale(g, (1.f - p.fy) * p.fx));
   if (p.fy > 0.f) {
@@ -354,6 +422,13 @@ hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
   hipError_t err;
 
   hipLaunchKernelGGL(pl_gather_kernel, pix_grid(NN, C), blk, 0, st, b);
+  if (a.fshift) {
+    // Fourier-shift patch (one slice): o = F^-1(S F w)
+    if (S != 1 || a.mode == MODE_APPLY_A || a.mode == MODE_APPLY_AH) return hipErrorNotSupported;
+    if ((err = launch_fft2(b.obuf, C, N, a.tw, false, st)) != hipSuccess) return err;
+    hipLaunchKernelGGL(pl_fs_shift_kernel, pix_grid(NN, C), blk, 0, st, b, 0);
+    if ((err = launch_fft2(b.obuf, C, N, a.tw, true, st)) != hipSuccess) return err;
+  }
   // incident probe of every position: per-position copy when weighted, else broadcast
   const float2* P0 = a.probe;
   size_t P0_stride = 0;
@@ -429,10 +504,17 @@ hipError_t run_plain_chunk(PlainArgs b, hipStream_t st) {
     hipLaunchKernelGGL(pl_probe_grad_kernel, pix_grid(NN, a.E * M), blk, 0, st, b);
   if ((a.want & WANT_WEIGHTS) && a.weights && a.w_part)
     hipLaunchKernelGGL(pl_weight_grad_kernel, dim3(C, a.E), blk, 0, st, b);
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && a.pos_part;
+  if (a.fshift && ((a.want & WANT_OBJ) || want_pos)) {
+    // G = F g_o: the position gradient from G and S X, then the window gradient F^-1(conj(S) G)
+    if ((err = launch_fft2(b.gbuf, C, N, a.tw, false, st)) != hipSuccess) return err;
+    if (want_pos) hipLaunchKernelGGL(pl_fs_posgrad_kernel, dim3(C), blk, 0, st, b);
+    hipLaunchKernelGGL(pl_fs_shift_kernel, pix_grid(NN, C), blk, 0, st, b, 1);
+    if ((err = launch_fft2(b.gbuf, C, N, a.tw, true, st)) != hipSuccess) return err;
+  }
   if ((a.want & WANT_OBJ) && a.gobj)
     for (int s = 0; s < S; ++s) hipLaunchKernelGGL(pl_scatter_kernel, pix_grid(NN, C), blk, 0, st, b, s);
-  if ((a.want & WANT_POS) && a.mode == MODE_FWD_ADJ && a.pos_part)
-    hipLaunchKernelGGL(pl_posgrad_kernel, dim3(C), blk, 0, st, b);
+  if (want_pos && !a.fshift) hipLaunchKernelGGL(pl_posgrad_kernel, dim3(C), blk, 0, st, b);
   return hipGetLastError();
 }
 

@@ -45,9 +45,9 @@ def test_exports_every_declared_symbol():
     (dict(frame=64, n_slices=2, obj_h=200, obj_w=200, det_lambda_z=40.0), 7),  # and one slice
     (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=float("inf")), 4),
     (dict(frame=128, obj_h=300, obj_w=300, subpixel="fourier"), 0),
-    (dict(frame=256, obj_h=600, obj_w=600, subpixel="fourier"), 7),            # Fourier shift: N <= 128,
-    (dict(frame=64, n_slices=3, obj_h=200, obj_w=200, subpixel="fourier"), 7), # one slice,
-    (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=5.0, subpixel="fourier"), 7),  # far field
+    (dict(frame=256, obj_h=600, obj_w=600, subpixel="fourier"), 0),            # Fourier shift of 256^2: per-step form
+    (dict(frame=64, n_slices=3, obj_h=200, obj_w=200, subpixel="fourier"), 7), # Fourier shift needs one slice
+    (dict(frame=64, obj_h=200, obj_w=200, det_lambda_z=5.0, subpixel="fourier"), 7),  # and the far field
     (dict(frame=64, obj_h=200, obj_w=200, subpixel=3), 1),
     (dict(frame=512, obj_h=600, obj_w=600000), 2),                           # window span over 2^31 bytes
     (dict(frame=128, obj_h=600, obj_w=600000), 0),
