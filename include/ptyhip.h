@@ -102,7 +102,8 @@ typedef struct {
   int32_t frame;        /* N: 16, 32, 64, 128, 256 or 512 */
   int32_t n_modes;      /* M: 1..64 incoherent probe modes (Sec. 2.1) */
   int32_t n_eig;        /* E: 1..16 eigenprobes (OPR, Sec. 2.1); 1 = none */
-  int32_t n_slices;     /* S: 1..64 multislice slices (Sec. 2.1) */
+  int32_t n_slices;     /* S: 1..64 multislice slices (Sec. 2.1); multislice plans of 256^2 and
+                           512^2 frames run the per-step form (no PTYHIP_GRAD_LAMBDA_Z there) */
   int32_t obj_h, obj_w; /* object size per slice, >= N each, <= 2^20 each, at most 4e9 pixels
                            over all slices; for N >= 256 also (N + 1) * obj_w * 8 < 2^31
                            (byte span of a patch window); otherwise PTYHIP_ESHAPE */

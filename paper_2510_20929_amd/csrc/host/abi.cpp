@@ -139,9 +139,11 @@ ptyhip_status plan_init(Plan* p, const ptyhip_desc& d, int maxK, const ptyhip_tu
   } else {
     p->threads = fused_big_threads(N, p->tune.variant);
     p->scratch_stride = fused_big_scratch_elems(N, S, M, E, &p->pacc_off);
-    // the four-step kernel models the far field with the bilinear patch; near-field and
-    // Fourier-shift plans of these frame sizes run the per-step form
+    // the four-step kernel models one slice, the far field and the bilinear patch;
+    // multislice, near-field and Fourier-shift plans of these frame sizes run the
+    // per-step form
     p->big_fused_ready = S == 1 && d.propagation == PTYHIP_PROP_FAR && d.subpixel == PTYHIP_SUBPIXEL_BILINEAR;
+    if (!p->big_fused_ready) p->scratch_stride = 0;  // no fused kernel: no workgroup scratch
   }
   // persistent grid: one workgroup per CU (the on-chip frame or the line blocks of the
   // four-step transforms fill most of a CU's LDS), two for the four-step layout with
@@ -228,7 +230,6 @@ ptyhip_status validate_desc(const ptyhip_desc* d) {
   if (!std::isfinite(d->poisson_eps) || d->poisson_eps < 0.f) return PTYHIP_ENONFINITE;
   if (!std::isfinite(d->lambda_z)) return PTYHIP_ENONFINITE;
   if (!std::isfinite(d->norm_count)) return PTYHIP_ENONFINITE;
-  if (d->n_slices > 1 && d->frame > 128) return PTYHIP_EUNSUPPORTED;
   if (d->propagation != PTYHIP_PROP_FAR && d->propagation != PTYHIP_PROP_NEAR) return PTYHIP_EINVAL;
   if (d->propagation == PTYHIP_PROP_NEAR) {
     if (!std::isfinite(d->det_lambda_z)) return PTYHIP_ENONFINITE;

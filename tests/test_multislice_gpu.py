@@ -55,6 +55,26 @@ def test_multislice_small(N, S, M, E):
         compare(got, ref, grads, tag=f"ms N={N} S={S} {'plain' if plain else 'fused'}")
 
 
+@pytest.mark.parametrize("N,S,M,E,loss", [(256, 3, 2, 1, "amplitude"), (512, 2, 1, 2, "poisson")])
+def test_multislice_large_frames_per_step_form(N, S, M, E, loss):
+    """Multislice plans of 256^2 and 512^2 frames run the per-step form (the four-step
+    kernel models one slice) against the oracle; the slice-spacing gradient is refused."""
+    from paper_2510_20929_amd import PtyhipError
+    from gpu_util import dev
+    start, I = custom_problem(320 + N + S, N, M, E, S, N + 96, 6, lz=N / 8.0, loss=loss,
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    plan = _plan(start)
+    got = run_gpu(plan, start, I, grads)
+    compare(got, ref, grads, tag=f"ms per-step N={N} S={S} M={M} E={E}")
+    assert got["flags"] == 0
+    w = None if start.weights is None else dev(start.weights)
+    with pytest.raises(PtyhipError):
+        plan.forward_adjoint(dev(start.obj), dev(start.probe), dev(start.positions), dev(I), weights=w,
+                             grads=("obj", "lambda_z"))
+
+
 @pytest.mark.parametrize("tune", [None, {"recompute": 1}, {"variant": 1, "grid": 16},
                                   {"variant": 1, "recompute": 1, "grid": 16}],
                          ids=["store", "recompute", "1024-store-grid16", "1024-recompute-grid16"])
