@@ -5,7 +5,7 @@ import ctypes
 import numpy as np
 import pytest
 
-from gpu_util import compare, custom_problem, dev, run_gpu, run_oracle, torch_cuda
+from gpu_util import compare, custom_problem, dev, rel_l2, run_gpu, run_oracle, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +46,46 @@ def test_bad_position_is_dropped_and_latched(N, kind, plain):
     compare(got, ref, grads, tag=f"{kind} {'plain' if plain else 'fused'}")
     plan.clear_error()
     assert plan.get_error() == 0
+
+
+@pytest.mark.parametrize("model", ["near", "fourier", "multislice"])
+def test_per_step_models_of_large_frames_drop_bad_positions_and_shard(model):
+    """256^2 near-field, Fourier-shift and multislice plans (per-step form): a position
+    outside the object is latched and dropped with the rest exact, and two shards
+    accumulated with the global normaliser equal the whole call."""
+    torch = torch_cuda()
+    from dataclasses import replace
+    from paper_2510_20929_amd import FLAG_BOUNDS, Plan
+    N = 256
+    kw = {"near": dict(det_lambda_z=(N / 2.0) ** 2 / 50.0), "fourier": dict(subpixel="fourier"),
+          "multislice": dict(lz=N / 8.0)}[model]
+    S = 2 if model == "multislice" else 1
+    p, I = custom_problem(47, N, 2, 1, S, N + 96, 8, **kw)
+    bad = 3
+    pos = p.positions.copy()
+    pos[bad] = (N + 90.0, 3.0)
+    q = replace(p, positions=pos)
+    grads = ("obj", "probe", "pos")
+    keep = np.array([k for k in range(p.K) if k != bad])
+    ref = run_oracle(q.subset(keep), I[keep], grads, norm_count=p.K)
+    plan = Plan.for_problem(q)
+    got = run_gpu(plan, q, I, grads, want_ipred=False)
+    assert got["flags"] & FLAG_BOUNDS
+    assert np.all(got["g_pos"][bad] == 0)
+    got["g_pos"] = got["g_pos"][keep]
+    compare(got, ref, grads, tag=f"{model} 256 bad position")
+    plan.clear_error()
+    sp = Plan.for_problem(p, norm_count=p.K)
+    o, u, r, m = dev(p.obj), dev(p.probe), dev(p.positions), dev(I)
+    whole = sp.forward_adjoint(o, u, r, m, grads=("obj", "probe"))
+    whole = {k: v.clone() for k, v in whole.items()}
+    acc = None
+    for a_, b_ in ((0, 3), (3, p.K)):
+        acc = sp.forward_adjoint(o, u, r[a_:b_].contiguous(), m[a_:b_].contiguous(), grads=("obj", "probe"),
+                                 accumulate=acc is not None, out=acc)
+    torch.cuda.synchronize()
+    for key in ("loss", "g_obj", "g_probe"):
+        assert rel_l2(acc[key].cpu().numpy(), whole[key].cpu().numpy()) <= 1e-5, key
 
 
 def test_host_errors_launch_nothing():
