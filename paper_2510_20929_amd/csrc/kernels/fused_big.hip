@@ -62,47 +62,59 @@ __global__ __launch_bounds__(256) void probe_reduce_big_kernel(const float2* __r
 // part[s][e][m][p] = sum over the positions kk of split s of w[kk][e] gP[kk][m][p]
 // (positions without a valid window are skipped); then the splits are added in order.
 // With one split the sums go straight to the output (added to it when `accumulate`).
+// A thread takes two neighbouring pixels (one 16-byte load per position; M N^2 is even
+// and every staged frame starts 16-byte aligned), with the loads of eight positions in
+// flight together; each pixel's terms are still added in position order.
+// WEIGHTED = false: no weights, one eigenprobe with weight 1.
+template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void eig_stage_kernel(const float2* __restrict__ gp, const float* __restrict__ w,
                                                         const int* __restrict__ valid, int n, int E, int M, int NN,
                                                         int splits, float2* __restrict__ part, int accumulate) {
+  constexpr int NB = 8;
+  constexpr int EM = WEIGHTED ? 16 : 1;
   const size_t MN = size_t(M) * NN;
   const int s = blockIdx.y;
   const int per = (n + splits - 1) / splits;
   const int k0 = s * per, k1 = min(n, k0 + per);
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < MN; g += size_t(gridDim.x) * blockDim.x) {
-    float2 acc[16];
+  const size_t step = size_t(gridDim.x) * blockDim.x * 2;
+  for (size_t g = (size_t(blockIdx.x) * blockDim.x + threadIdx.x) * 2; g < MN; g += step) {
+    float2 acc[2][EM];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = make_float2(0.f, 0.f);
-    // four positions' loads in flight together; they are added in position order
-    for (int kk = k0; kk < k1; kk += 4) {
-      float2 v[4];
-      bool on[4];
+    for (int e = 0; e < EM; ++e) acc[0][e] = acc[1][e] = make_float2(0.f, 0.f);
+    for (int kk = k0; kk < k1; kk += NB) {
+      float4 v[NB];
+      bool on[NB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < NB; ++u) {
         on[u] = kk + u < k1 && valid[kk + u];
-        v[u] = on[u] ? gp[size_t(kk + u) * MN + g] : make_float2(0.f, 0.f);
+        v[u] = on[u] ? *reinterpret_cast<const float4*>(gp + size_t(kk + u) * MN + g) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < NB; ++u) {
         if (!on[u]) continue;
-        if (w == nullptr) {  // no weights: one eigenprobe with weight 1
-          acc[0] = cadd(acc[0], v[u]);
+        const float2 v0 = make_float2(v[u].x, v[u].y), v1 = make_float2(v[u].z, v[u].w);
+        if constexpr (!WEIGHTED) {
+          acc[0][0] = cadd(acc[0][0], v0);
+          acc[1][0] = cadd(acc[1][0], v1);
           continue;
         }
         const float* wk = w + size_t(kk + u) * E;
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
+        for (int e = 0; e < EM; ++e)
           if (e < E) {
-            acc[e].x = fmaf(wk[e], v[u].x, acc[e].x);
-            acc[e].y = fmaf(wk[e], v[u].y, acc[e].y);
+            acc[0][e].x = fmaf(wk[e], v0.x, acc[0][e].x);
+            acc[0][e].y = fmaf(wk[e], v0.y, acc[0][e].y);
+            acc[1][e].x = fmaf(wk[e], v1.x, acc[1][e].x);
+            acc[1][e].y = fmaf(wk[e], v1.y, acc[1][e].y);
           }
       }
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e)
+    for (int e = 0; e < EM; ++e)
       if (e < E) {
-        float2& o = part[(size_t(s) * E + e) * MN + g];
-        o = accumulate ? cadd(o, acc[e]) : acc[e];
+        float2* o = part + (size_t(s) * E + e) * MN + g;
+        o[0] = accumulate ? cadd(o[0], acc[0][e]) : acc[0][e];
+        o[1] = accumulate ? cadd(o[1], acc[1][e]) : acc[1][e];
       }
   }
 }
@@ -121,16 +133,20 @@ __global__ void eig_combine_kernel(const float2* __restrict__ part, int splits, 
 hipError_t launch_eig_stage_reduce(const float2* gp, const float* w, const int* valid, int n, int E, int M, int N,
                                    int splits, float2* part, float2* g_probe, int accumulate, hipStream_t st) {
   const size_t MN = size_t(M) * N * N;
-  size_t bx = (MN + 255) / 256;
+  size_t bx = (MN / 2 + 255) / 256;  // two pixels per thread
   if (bx > 4096) bx = 4096;
   splits = std::max(1, std::min(splits, n / 64));
   if (splits == 1) {
-    hipLaunchKernelGGL(eig_stage_kernel, dim3(unsigned(bx), 1u), dim3(256), 0, st, gp, w, valid, n, E, M, N * N, 1,
-                       g_probe, accumulate);
+    if (w) hipLaunchKernelGGL(eig_stage_kernel<true>, dim3(unsigned(bx), 1u), dim3(256), 0, st, gp, w, valid, n, E, M,
+                              N * N, 1, g_probe, accumulate);
+    else hipLaunchKernelGGL(eig_stage_kernel<false>, dim3(unsigned(bx), 1u), dim3(256), 0, st, gp, w, valid, n, E, M,
+                            N * N, 1, g_probe, accumulate);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(eig_stage_kernel, dim3(unsigned(bx), unsigned(splits)), dim3(256), 0, st, gp, w, valid, n, E, M,
-                     N * N, splits, part, 0);
+  if (w) hipLaunchKernelGGL(eig_stage_kernel<true>, dim3(unsigned(bx), unsigned(splits)), dim3(256), 0, st, gp, w, valid,
+                            n, E, M, N * N, splits, part, 0);
+  else hipLaunchKernelGGL(eig_stage_kernel<false>, dim3(unsigned(bx), unsigned(splits)), dim3(256), 0, st, gp, w, valid,
+                          n, E, M, N * N, splits, part, 0);
   const size_t total = size_t(E) * MN;
   size_t b2 = (total + 255) / 256;
   if (b2 > 16384) b2 = 16384;
