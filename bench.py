@@ -211,6 +211,10 @@ def kernel_name(plan, prob, tune):
     if prob.S > 1:
         return "fused_small_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
+    if prob.N == 128 and v >= 5:
+        # working frame resident in LDS; dl/dI in registers (6) or scratch (5)
+        return "fused_small_lds_kernel<%d, %d, %d, %s>" % (prob.N, info["threads"], loss,
+                                                            "true" if v == 6 else "false")
     rv = "true" if v in (2, 3, 4) else "false"      # patch in registers
     goreg = "true" if v in (2, 3) else "false"      # patch gradient in registers
     if getattr(prob, "det_lambda_z", None) is not None:

@@ -128,7 +128,12 @@ typedef struct {
   int32_t variant;      /* on-chip fused kernel (64^2, 128^2): 0 = 512 threads, patch in scratch;
                            1 = 1024 (128^2) / 256 (64^2) threads; 2 = 512 threads, patch and
                            patch gradient in registers; 3 = as 2 with 1024 / 256 threads;
-                           4 = as 3 with the patch gradient in scratch.
+                           4 = as 3 with the patch gradient in scratch; 128^2 only, one slice,
+                           far field, bilinear patch, whole positions (PTYHIP_EUNSUPPORTED
+                           otherwise): 5 = 1024 threads with the working frame resident in
+                           LDS, patch and running patch gradient in registers, dl/dI in
+                           scratch, far fields always recomputed; 6 = as 5 with dl/dI in
+                           registers.
                            Four-step fused kernel (256^2, 512^2): 0 = one workgroup of 1024
                            threads per CU; 1 = two per CU (512 / 256 threads, smaller line
                            blocks); other values are PTYHIP_EINVAL */

@@ -79,10 +79,12 @@ def save_cache(cache: Dict[str, dict], path: str = DEFAULT_CACHE) -> None:
     os.replace(tmp, path)
 
 
-def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E: int = 1) -> List[dict]:
+def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E: int = 1,
+                    lds_ok: bool = True) -> List[dict]:
     """Thread layout x far-field store/recompute x persistent grid; with few positions per
     call and several modes (K below two workgroups per CU), also the mode-split form with
-    enough groups to give every CU one or two (position, group) items."""
+    enough groups to give every CU one or two (position, group) items. ``lds_ok``: the
+    LDS-resident 128^2 layouts (5, 6; one slice, far field, bilinear patch) apply."""
     cus = _cus()
     out = []
     variants = [0, 1, 2, 3, 4] if N in (64, 128) else [0, 1]
@@ -92,6 +94,10 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E
         for r in recomputes:
             for g in grids:
                 out.append({"variant": v, "recompute": r, "grid": g})
+    if N == 128 and S == 1 and lds_ok:
+        # far fields are always recomputed in these layouts
+        for v in (5, 6):
+            out.append({"variant": v, "recompute": 1, "grid": 0})
     # single eigenprobe: the probe gradients staged per position instead of accumulated
     # in the workgroups' scratch (a streaming write and a separate reduction in place of
     # a read-modify-write per mode)
@@ -172,7 +178,7 @@ def tune_plan(shape: dict, obj, probe, positions, I_meas, weights=None, grads=("
     results = []
     best = None
     split_ok = shape.get("det_lambda_z") is None and shape.get("subpixel", "bilinear") == "bilinear"
-    for cand in plan_candidates(shape["N"], shape["M"], shape["S"], K, split_ok, shape["E"]):
+    for cand in plan_candidates(shape["N"], shape["M"], shape["S"], K, split_ok, shape["E"], lds_ok=split_ok):
         plan = make(cand)
         out = plan.forward_adjoint(obj, probe, positions, I_meas, weights=weights, grads=grads)
         torch.cuda.synchronize()

@@ -486,4 +486,152 @@ struct LineTileW {
   }
 };
 
+// ----------------------------------------------------------------------------- LDS-resident frame
+// A whole N x N frame kept in LDS (natural order, pitch P = N + N1) and transformed in
+// place by T = N * N1 threads, rows first, then columns. Each line is served by N1 lanes
+// of one wavefront, so the two stages of a line exchange through LDS with only a
+// compiler fence (a wave's LDS operations execute in order);
+// a 2D transform needs a block barrier before the rows, between rows and columns, and
+// after the columns. Registers hold one line stage at a time (N2 elements per thread),
+// which leaves the rest of the register file to the caller's per-pixel state.
+// Each line runs the same split as Frame2D: N1 register DFTs of size N2 over
+// x[n1 + N1 n2], the twiddle W_N^{n1 k2}, then for each k2 a DFT of size N1 giving
+// X[k2 + N2 k1]; the inverse is the same split with W_N^-1 (unnormalised). Stage-1
+// results are stored at N1 k2 + (n1 XOR (k2 mod N1)), as in LineTile.
+template <int N, int T>
+struct FrameLds {
+  static constexpr int N1 = Split<N>::N1;
+  static constexpr int N2 = Split<N>::N2;
+  static_assert(T == N * N1, "one line per N1 threads");
+  static_assert(WAVE % N1 == 0, "the N1 threads of a line must share a wavefront");
+  static constexpr int LW = WAVE / N1;  // lines per wave in the column pass
+  static constexpr int P = N + N1;
+  static constexpr int LDS_ELEMS = N * P;
+  static constexpr int EL = N * N / T;  // pixels per thread in the element passes
+  __device__ __forceinline__ static int sw(int n1, int k2) { return N1 * k2 + (n1 ^ (k2 & (N1 - 1))); }
+  __device__ __forceinline__ static void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+  // every line (element i of line ln at lds[ln LS + i ES]) transformed in place, times
+  // `scale`. Rows (ES = 1): line t / N1, lane q = t mod N1 (a half-wave reads four rows'
+  // consecutive cells); columns (ES = P): the lines of a wave are WAVE / N1 adjacent
+  // columns and lane q = (t mod WAVE) / N1, so a half-wave reads WAVE / N1 consecutive
+  // cells in each of four rows (with P = N + N1 both fall in distinct LDS banks).
+  template <bool INV, bool COLS>
+  __device__ __forceinline__ static void lines(float2* lds, int LS, int ES, const float2* __restrict__ tw,
+                                               float scale) {
+    const int t = opaque_tid();
+    const int q = COLS ? (t % WAVE) / LW : t % N1;
+    const int ln = COLS ? (t / WAVE) * LW + t % LW : t / N1;
+    float2* base = lds + ln * LS;
+    float2 u[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[(q + N1 * n2) * ES];
+    lines_from<INV, COLS>(lds, LS, ES, tw, scale, u);
+  }
+  // as lines, with the thread's stage-1 input x[q + N1 n2] already in u[n2]
+  template <bool INV, bool COLS>
+  __device__ __forceinline__ static void lines_from(float2* lds, int LS, int ES, const float2* __restrict__ tw,
+                                                    float scale, float2 (&u)[N2]) {
+    const int t = opaque_tid();
+    const int q = COLS ? (t % WAVE) / LW : t % N1;
+    const int ln = COLS ? (t / WAVE) * LW + t % LW : t / N1;
+    float2* base = lds + ln * LS;
+    Dft<N2, INV>::run(u);
+    // twiddle and store four at a time (the caller's per-pixel state shares the registers)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      if (k2 > 0) u[k2] = INV ? cmul_conjb(u[k2], tw[q * k2]) : cmul(u[k2], tw[q * k2]);
+      base[sw(q, k2) * ES] = u[k2];
+      if (k2 % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_fence();
+#pragma unroll
+    for (int jj = 0; jj < N2 / N1; ++jj) {
+      const int k2 = q + N1 * jj;
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) u[jj * N1 + n1] = base[sw(n1, k2) * ES];
+      Dft<N1, INV>::run(&u[jj * N1]);
+    }
+    wave_fence();
+#pragma unroll
+    for (int jj = 0; jj < N2 / N1; ++jj)
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) base[(q + N1 * jj + N2 * k1) * ES] = cscale(u[jj * N1 + k1], scale);
+  }
+
+  // Column and row of element e (0 <= e < N2) that cols_to_regs leaves in thread t:
+  // column col(t), row row(t, e); these are the cells the thread's column pass reads and
+  // writes, so a caller that writes exactly them needs no barrier before cols().
+  __device__ __forceinline__ static int col(int t) { return (t / WAVE) * LW + t % LW; }
+  __device__ __forceinline__ static int row(int t, int e) { return (t % WAVE) / LW + N1 * (e / N1) + N2 * (e % N1); }
+
+  // The two passes on their own; the caller places the block barriers. A row pass reads
+  // and writes only the rows of its wave, and thread t only the cells (t / N1, t mod N1 +
+  // N1 j), which it may therefore fill or read itself without a barrier; a column pass
+  // touches only the columns of its wave. Rows and columns need a barrier between them.
+  template <bool INV>
+  __device__ __forceinline__ static void rows(float2* lds, const float2* __restrict__ tw, float scale) {
+    lines<INV, false>(lds, P, 1, tw, scale);
+  }
+  template <bool INV>
+  __device__ __forceinline__ static void cols(float2* lds, const float2* __restrict__ tw, float scale) {
+    lines<INV, true>(lds, 1, P, tw, scale);
+  }
+  // Row (column) pass whose stage-1 input is already in registers: u[n2] is the cell the
+  // pass would read, (t / N1, t mod N1 + N1 n2) for rows, (row(t, e), col(t)) with
+  // e = reg_of(n2) for columns (so that a caller holding the cols_to_regs layout passes
+  // v[reg_of(n2)] as u[n2]).
+  template <bool INV>
+  __device__ __forceinline__ static void rows_from(float2* lds, const float2* __restrict__ tw, float scale,
+                                                   float2 (&u)[N2]) {
+    lines_from<INV, false>(lds, P, 1, tw, scale, u);
+  }
+  template <bool INV>
+  __device__ __forceinline__ static void cols_from(float2* lds, const float2* __restrict__ tw, float scale,
+                                                   float2 (&u)[N2]) {
+    lines_from<INV, true>(lds, 1, P, tw, scale, u);
+  }
+  // row(t, reg_of(n2)) = (t mod WAVE) / LW + N1 n2
+  __host__ __device__ static constexpr int reg_of(int n2) { return (n2 % (N2 / N1)) * N1 + n2 / (N2 / N1); }
+
+  // Forward column pass that ends in registers: v[e] is frequency (row(t, e), col(t)),
+  // times `scale`; the LDS cells keep the stage-1 intermediate.
+  __device__ __forceinline__ static void cols_to_regs(float2* lds, const float2* __restrict__ tw, float scale,
+                                                      float2 (&v)[N2]) {
+    const int t = opaque_tid();
+    const int q = (t % WAVE) / LW;
+    float2* base = lds + col(t);
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) v[n2] = base[(q + N1 * n2) * P];
+    Dft<N2, false>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      if (k2 > 0) v[k2] = cmul(v[k2], tw[q * k2]);
+      base[sw(q, k2) * P] = v[k2];
+      if (k2 % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_fence();
+#pragma unroll
+    for (int jj = 0; jj < N2 / N1; ++jj) {
+      const int k2 = q + N1 * jj;
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) v[jj * N1 + n1] = base[sw(n1, k2) * P];
+      Dft<N1, false>::run(&v[jj * N1]);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) v[jj * N1 + k1] = cscale(v[jj * N1 + k1], scale);
+    }
+  }
+
+  // 2D transform of the frame in LDS (forward: exp(-2 pi i k.n / N); INV: the conjugate
+  // kernel), times `scale`; block barriers before, between the passes and after
+  template <bool INV>
+  __device__ __forceinline__ static void transform(float2* lds, const float2* __restrict__ tw, float scale) {
+    __syncthreads();
+    rows<INV>(lds, tw, 1.f);
+    __syncthreads();
+    cols<INV>(lds, tw, scale);
+    __syncthreads();
+  }
+};
+
 }  // namespace ptyhip

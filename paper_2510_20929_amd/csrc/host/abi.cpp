@@ -598,10 +598,15 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
   ptyhip_status s = validate_desc(desc);
   if (s != PTYHIP_OK) return s;
   if (max_positions < 0) return PTYHIP_EBOUNDS;
-  if (tune && (tune->variant < 0 || tune->variant > (desc->frame <= 128 ? 4 : 1) || tune->grid < 0 ||
+  if (tune && (tune->variant < 0 || tune->variant > (desc->frame == 128 ? 6 : desc->frame < 128 ? 4 : 1) || tune->grid < 0 ||
                tune->plain_chunk < 0 || tune->recompute < 0 || tune->mode_groups < 0 || tune->probe_stage < 0 ||
                tune->probe_stage > 1))
     return PTYHIP_EINVAL;
+  // the LDS-resident 128^2 layouts model one slice, the far field and the bilinear patch
+  if (tune && desc->frame == 128 && tune->variant >= 5 &&
+      (desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR || desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR ||
+       tune->mode_groups > 1))
+    return PTYHIP_EUNSUPPORTED;
   if (tune && tune->mode_groups > 1 &&
       (desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||
        desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR))

@@ -1,6 +1,7 @@
 // Fused forward + adjoint kernels for frames that stay on chip (N <= 128): the
 // single-slice kernel (a thin wrapper over small_body) and the multislice kernel.
 #include "launch.hpp"
+#include "lds_body.hpp"
 #include "small_body.hpp"
 
 namespace ptyhip {
@@ -9,6 +10,13 @@ template <int N, int T, int LOSS, bool RV, bool GOREG = RV>
 __global__ __launch_bounds__(T) void fused_small_kernel(CallArgs a) {
   __shared__ SmallShared<N, T> sh;
   small_body<N, T, LOSS, RV, GOREG>(a, sh, blockIdx.x, gridDim.x);
+}
+
+// the working frame resident in LDS, per-position state in registers (variants 5, 6)
+template <int N, int T, int LOSS, bool CFREG>
+__global__ __launch_bounds__(T) void fused_small_lds_kernel(CallArgs a) {
+  __shared__ LdsShared<N, T> sh;
+  lds_body<N, T, LOSS, CFREG>(a, sh, blockIdx.x, gridDim.x);
 }
 
 template <int N, int T, int LOSS>
@@ -232,8 +240,9 @@ __global__ __launch_bounds__(T) void fused_small_ms_kernel(CallArgs a) {
 
 // ----------------------------------------------------------------------------- probe reduction
 // g_probe[e][m][pix] (+)= sum over workgroups of their accumulator frames, mapping the
-// scratch element i*T + t back to pixel a_pix(t, i).
-template <int N, int T>
+// scratch element i*T + t back to pixel a_pix(t, i) (NAT: the accumulator is in natural
+// pixel order, as the LDS-resident layouts keep it).
+template <int N, int T, bool NAT = false>
 __global__ __launch_bounds__(256) void probe_reduce_kernel(const float2* __restrict__ scratch, size_t stride,
                                                            size_t pacc_off, int groups, int EM, float2* g_probe,
                                                            int accumulate) {
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(256) void probe_reduce_kernel(const float2* __restr
     s = cadd(cadd(part[0][lane], part[1][lane]), cadd(part[2][lane], part[3][lane]));
     const size_t em = g / C::NN, r = g % C::NN;
     const int i = int(r / T), t = int(r % T);
-    float2* dst = g_probe + em * C::NN + C::a_pix(t, i);
+    float2* dst = g_probe + em * C::NN + (NAT ? int(r) : C::a_pix(t, i));
     *dst = accumulate ? cadd(*dst, s) : s;
   }
 }
@@ -294,11 +303,11 @@ static hipError_t launch_small_t(const CallArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N, int T>
+template <int N, int T, bool NAT = false>
 static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, int accumulate, hipStream_t st) {
   const size_t n = size_t(a.E) * a.M * N * N;
   const size_t blocks = (n + 63) / 64;
-  hipLaunchKernelGGL((probe_reduce_kernel<N, T>), dim3(unsigned(blocks)), dim3(256), 0, st, a.scratch,
+  hipLaunchKernelGGL((probe_reduce_kernel<N, T, NAT>), dim3(unsigned(blocks)), dim3(256), 0, st, a.scratch,
                      a.scratch_stride, a.pacc_off, grid, a.E * a.M, g_probe, accumulate);
   return hipGetLastError();
 }
@@ -306,9 +315,11 @@ static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, i
 // variants: 0 = 512 threads, scratch-resident patch; 1 = 1024 (128^2) or 256 (64^2)
 // threads, scratch-resident patch; 2 = 512 threads, register-resident patch;
 // 3 = 1024 (128^2) or 256 (64^2) threads, register-resident patch and patch gradient;
-// 4 = as 3 with the patch gradient in scratch
+// 4 = as 3 with the patch gradient in scratch; 5, 6 (128^2 only) = 1024 threads, the
+// working frame resident in LDS, patch and running patch gradient in registers, dl/dI
+// in scratch (5) or in registers (6)
 int fused_small_threads(int N, int variant) {
-  const bool wide = variant == 1 || variant == 3 || variant == 4;
+  const bool wide = variant == 1 || variant == 3 || variant == 4 || (N == 128 && variant >= 5);
   switch (N) {
     case 16: return 64;
     case 32: return 128;
@@ -328,6 +339,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
   else if (fshift) base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1) + fr;  // + shifted window spectrum
   else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
   else if (variant == 4 && N >= 64) base = fr / 2 + fr + (recompute ? 0 : fr * size_t(M - 1));
+  else if (variant >= 5 && N == 128) base = variant == 5 ? fr / 2 : 0;  // far fields always recomputed
   else base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1);
   *pacc_off = base;
   return base + fr * size_t(E) * M;
@@ -345,6 +357,18 @@ hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, h
       if (variant == 2) return launch_small_t<64, 512, true>(a, grid, st);
       return launch_small_t<64, 512>(a, grid, st);
     case 128:
+      if (variant >= 5) {
+        // single slice, far field, bilinear patch (the plan checks)
+        if (a.near || a.S > 1) return hipErrorInvalidValue;
+        if (variant == 5) {
+          if (a.loss == 0) hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 0, false>), dim3(grid), dim3(1024), 0, st, a);
+          else hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 1, false>), dim3(grid), dim3(1024), 0, st, a);
+        } else {
+          if (a.loss == 0) hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 0, true>), dim3(grid), dim3(1024), 0, st, a);
+          else hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 1, true>), dim3(grid), dim3(1024), 0, st, a);
+        }
+        return hipGetLastError();
+      }
       if (variant == 1) return launch_small_t<128, 1024>(a, grid, st);
       if (variant == 3) return launch_small_t<128, 1024, true>(a, grid, st);
       if (variant == 4) return launch_small_t<128, 1024, true, false>(a, grid, st);
@@ -363,6 +387,7 @@ hipError_t launch_probe_reduce_small(const CallArgs& a, int N, int variant, int 
       return fused_small_threads(64, variant) == 256 ? probe_reduce_t<64, 256>(a, grid, g_probe, accumulate, st)
                                                      : probe_reduce_t<64, 512>(a, grid, g_probe, accumulate, st);
     case 128:
+      if (variant >= 5) return probe_reduce_t<128, 1024, true>(a, grid, g_probe, accumulate, st);
       return fused_small_threads(128, variant) == 1024
                  ? probe_reduce_t<128, 1024>(a, grid, g_probe, accumulate, st)
                  : probe_reduce_t<128, 512>(a, grid, g_probe, accumulate, st);

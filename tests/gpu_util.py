@@ -208,6 +208,8 @@ def kernel_instance(prob, tune, threads):
     if prob.S > 1:
         return f"fused_small_ms_kernel<{prob.N},{threads},{loss}>"
     v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
+    if prob.N == 128 and v >= 5:
+        return f"fused_small_lds_kernel<{prob.N},{threads},{loss},{'true' if v == 6 else 'false'}>"
     rv = "true" if v in (2, 3, 4) else "false"
     goreg = "true" if v in (2, 3) else "false"
     return f"fused_small_kernel<{prob.N},{threads},{loss},{rv},{goreg}>"

@@ -18,7 +18,10 @@ def mi355x(monkeypatch):
 def test_candidates_on_chip(mi355x):
     c = autotune.plan_candidates(128, 4, 1, K=2000, split_ok=True, E=1)
     layouts = {(x["variant"], x["recompute"], x["grid"]) for x in c if "mode_groups" not in x and "probe_stage" not in x}
-    assert layouts == {(v, r, g) for v in range(5) for r in (0, 1) for g in (0, 512)}
+    assert layouts == {(v, r, g) for v in range(5) for r in (0, 1) for g in (0, 512)} | {(5, 1, 0), (6, 1, 0)}
+    # the LDS-resident layouts only where they apply (one slice, far field, bilinear patch)
+    assert not any(x["variant"] >= 5 for x in autotune.plan_candidates(128, 4, 1, K=2000, lds_ok=False))
+    assert not any(x["variant"] >= 5 for x in autotune.plan_candidates(64, 4, 1, K=2000))
     assert not any("mode_groups" in x for x in c)          # 2000 positions fill the GPU
     assert any(x.get("probe_stage") == 1 for x in c)         # one eigenprobe, one slice
     few = autotune.plan_candidates(128, 30, 1, K=50, split_ok=True, E=1)
@@ -33,7 +36,7 @@ def test_candidates_four_step_and_multislice(mi355x):
     assert {x["mode_groups"] for x in c if "mode_groups" in x} == {15}
     assert not any("probe_stage" in x for x in c)            # several eigenprobes are staged anyway
     ms = autotune.plan_candidates(128, 2, 8, K=100, split_ok=True, E=1)
-    assert not any("mode_groups" in x or "probe_stage" in x for x in ms)
+    assert not any("mode_groups" in x or "probe_stage" in x or x["variant"] >= 5 for x in ms)
 
 
 def test_shape_key_buckets_positions(mi355x):

@@ -30,9 +30,12 @@ def c1():
     {"variant": 4, "recompute": 0},
     {"variant": 1, "recompute": 1},
     {"variant": 0, "recompute": 0},
+    {"variant": 5, "recompute": 1},
+    {"variant": 6, "recompute": 1},
 ], ids=["bench-choice", "fused_small_kernel<128,1024,1,true,false>-recompute",
         "fused_small_kernel<128,1024,1,true,false>-store", "fused_small_kernel<128,1024,1,false,false>-recompute",
-        "fused_small_kernel<128,512,1,false,false>-store"])
+        "fused_small_kernel<128,512,1,false,false>-store", "fused_small_lds_kernel<128,1024,1,false>",
+        "fused_small_lds_kernel<128,1024,1,true>"])
 def test_config1_full_parity(c1, tune):
     from paper_2510_20929_amd import Plan
     start, I, ref = c1
