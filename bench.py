@@ -33,6 +33,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published)
 KERNEL_SOURCES = [
     "paper_2510_20929_amd/csrc/kernels/fused_small.hip",
     "paper_2510_20929_amd/csrc/kernels/small_body.hpp",
+    "paper_2510_20929_amd/csrc/kernels/lds_body.hpp",
     "paper_2510_20929_amd/csrc/device/fft.hpp",
     "paper_2510_20929_amd/csrc/device/model.hpp",
     "paper_2510_20929_amd/csrc/device/common.hpp",
