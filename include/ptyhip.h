@@ -315,7 +315,8 @@ ptyhip_status ptyhip_clear_error(ptyhip_plan plan, void* stream);
  *   desc, tune   problem and implementation choice as for ptyhip_plan_create_ex (tune
  *                may be NULL; its mode_groups and probe_stage fields are ignored: a
  *                workgroup always takes whole positions and accumulates the probe
- *                gradient in its own frames); N <= 128, one slice, far field (bilinear or
+ *                gradient in its own frames; variant 0-4 only, the LDS-resident 5 and 6 are
+ *                PTYHIP_EINVAL here); N <= 128, one slice, far field (bilinear or
  *                Fourier-shift patch), else PTYHIP_EUNSUPPORTED
  *   other args   as ptyhip_forward_adjoint (device pointers owned by the caller);
  *                PTYHIP_PLAIN is EUNSUPPORTED, PTYHIP_GRAD_LAMBDA_Z is EINVAL
