@@ -34,6 +34,7 @@ KERNEL_SOURCES = [
     "paper_2510_20929_amd/csrc/kernels/fused_small.hip",
     "paper_2510_20929_amd/csrc/kernels/small_body.hpp",
     "paper_2510_20929_amd/csrc/kernels/lds_body.hpp",
+    "paper_2510_20929_amd/csrc/kernels/lds_ms.hpp",
     "paper_2510_20929_amd/csrc/device/fft.hpp",
     "paper_2510_20929_amd/csrc/device/model.hpp",
     "paper_2510_20929_amd/csrc/device/common.hpp",
@@ -210,6 +211,8 @@ def kernel_name(plan, prob, tune):
     if prob.N >= 256:
         return "fused_big_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     if prob.S > 1:
+        if prob.N == 128 and (tune or {}).get("variant", 0) >= 5:
+            return "fused_small_lds_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
         return "fused_small_ms_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
     if prob.N == 128 and v >= 5:

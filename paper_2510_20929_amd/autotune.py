@@ -84,7 +84,7 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E
     """Thread layout x far-field store/recompute x persistent grid; with few positions per
     call and several modes (K below two workgroups per CU), also the mode-split form with
     enough groups to give every CU one or two (position, group) items. ``lds_ok``: the
-    LDS-resident 128^2 layouts (5, 6; one slice, far field, bilinear patch) apply."""
+    LDS-resident 128^2 layouts (5, 6; far field, bilinear patch) apply."""
     cus = _cus()
     out = []
     variants = [0, 1, 2, 3, 4] if N in (64, 128) else [0, 1]
@@ -94,10 +94,15 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E
         for r in recomputes:
             for g in grids:
                 out.append({"variant": v, "recompute": r, "grid": g})
-    if N == 128 and S == 1 and lds_ok:
-        # far fields are always recomputed in these layouts
-        for v in (5, 6):
-            out.append({"variant": v, "recompute": 1, "grid": 0})
+    if N == 128 and lds_ok:
+        if S == 1:
+            # far fields are always recomputed in these layouts
+            for v in (5, 6):
+                out.append({"variant": v, "recompute": 1, "grid": 0})
+        else:
+            # several slices: one LDS-resident kernel (incident waves stored or recomputed)
+            for r in recomputes:
+                out.append({"variant": 5, "recompute": r, "grid": 0})
     # single eigenprobe: the probe gradients staged per position instead of accumulated
     # in the workgroups' scratch (a streaming write and a separate reduction in place of
     # a read-modify-write per mode)

@@ -591,6 +591,36 @@ struct FrameLds {
                                                    float2 (&u)[N2]) {
     lines_from<INV, true>(lds, 1, P, tw, scale, u);
   }
+  // Row pass that ends in registers: h[i] is cell (t / N1, t mod N1 + N1 i) of the
+  // transformed rows, times `scale`; the LDS cells keep the stage-1 intermediate.
+  template <bool INV>
+  __device__ __forceinline__ static void rows_to_regs(float2* lds, const float2* __restrict__ tw, float scale,
+                                                      float2 (&h)[N2]) {
+    const int t = opaque_tid();
+    const int q = t % N1;
+    float2* base = lds + (t / N1) * P;
+    float2 u[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) u[n2] = base[q + N1 * n2];
+    Dft<N2, INV>::run(u);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      if (k2 > 0) u[k2] = INV ? cmul_conjb(u[k2], tw[q * k2]) : cmul(u[k2], tw[q * k2]);
+      base[sw(q, k2)] = u[k2];
+      if (k2 % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_fence();
+#pragma unroll
+    for (int jj = 0; jj < N2 / N1; ++jj) {
+      const int k2 = q + N1 * jj;
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) u[jj * N1 + n1] = base[sw(n1, k2)];
+      Dft<N1, INV>::run(&u[jj * N1]);
+    }
+    // output k2 + N2 k1 = q + N1 (jj + 2 k1) is the thread's cell i = jj + 2 k1
+#pragma unroll
+    for (int i = 0; i < N2; ++i) h[i] = cscale(u[reg_of(i)], scale);
+  }
   // row(t, reg_of(n2)) = (t mod WAVE) / LW + N1 n2
   __host__ __device__ static constexpr int reg_of(int n2) { return (n2 % (N2 / N1)) * N1 + n2 / (N2 / N1); }
 

@@ -2,6 +2,7 @@
 // single-slice kernel (a thin wrapper over small_body) and the multislice kernel.
 #include "launch.hpp"
 #include "lds_body.hpp"
+#include "lds_ms.hpp"
 #include "small_body.hpp"
 
 namespace ptyhip {
@@ -17,6 +18,13 @@ template <int N, int T, int LOSS, bool CFREG>
 __global__ __launch_bounds__(T) void fused_small_lds_kernel(CallArgs a) {
   __shared__ LdsShared<N, T> sh;
   lds_body<N, T, LOSS, CFREG>(a, sh, blockIdx.x, gridDim.x);
+}
+
+// multislice with the working frame resident in LDS (variants 5, 6 with several slices)
+template <int N, int T, int LOSS, bool LZ>
+__global__ __launch_bounds__(T) void fused_small_lds_ms_kernel(CallArgs a) {
+  __shared__ LdsShared<N, T> sh;
+  lds_ms_body<N, T, LOSS, LZ>(a, sh, blockIdx.x, gridDim.x);
 }
 
 template <int N, int T, int LOSS>
@@ -317,7 +325,8 @@ static hipError_t probe_reduce_t(const CallArgs& a, int grid, float2* g_probe, i
 // 3 = 1024 (128^2) or 256 (64^2) threads, register-resident patch and patch gradient;
 // 4 = as 3 with the patch gradient in scratch; 5, 6 (128^2 only) = 1024 threads, the
 // working frame resident in LDS, patch and running patch gradient in registers, dl/dI
-// in scratch (5) or in registers (6)
+// in scratch (5) or in registers (6); with several slices both run the LDS-resident
+// multislice kernel (dl/dI in scratch)
 int fused_small_threads(int N, int variant) {
   const bool wide = variant == 1 || variant == 3 || variant == 4 || (N == 128 && variant >= 5);
   switch (N) {
@@ -334,7 +343,7 @@ size_t fused_small_scratch_elems(int N, int S, int M, int E, int recompute, size
                                  bool near, bool fshift) {
   const size_t fr = size_t(N) * N;
   size_t base;
-  if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S));
+  if (S > 1) base = fr * (size_t(2) * S + (recompute ? 0 : size_t(M) * S)) + (variant >= 5 && N == 128 ? fr / 2 : 0);
   else if (near) base = fr * (2 + size_t(M));
   else if (fshift) base = fr * (M > 1 ? (recompute ? 2 : size_t(M) + 1) : 1) + fr;  // + shifted window spectrum
   else if ((variant == 2 || variant == 3) && N >= 64) base = fr / 2 + (recompute ? 0 : fr * size_t(M - 1));
@@ -358,8 +367,19 @@ hipError_t launch_fused_small(const CallArgs& a, int N, int variant, int grid, h
       return launch_small_t<64, 512>(a, grid, st);
     case 128:
       if (variant >= 5) {
-        // single slice, far field, bilinear patch (the plan checks)
-        if (a.near || a.S > 1) return hipErrorInvalidValue;
+        // far field, bilinear patch (the plan checks)
+        if (a.near) return hipErrorInvalidValue;
+        if (a.S > 1) {
+          const bool lz = (a.want & WANT_LZ) && a.mode == MODE_FWD_ADJ && a.lz_part != nullptr;
+          if (a.loss == 0) {
+            if (lz) hipLaunchKernelGGL((fused_small_lds_ms_kernel<128, 1024, 0, true>), dim3(grid), dim3(1024), 0, st, a);
+            else hipLaunchKernelGGL((fused_small_lds_ms_kernel<128, 1024, 0, false>), dim3(grid), dim3(1024), 0, st, a);
+          } else {
+            if (lz) hipLaunchKernelGGL((fused_small_lds_ms_kernel<128, 1024, 1, true>), dim3(grid), dim3(1024), 0, st, a);
+            else hipLaunchKernelGGL((fused_small_lds_ms_kernel<128, 1024, 1, false>), dim3(grid), dim3(1024), 0, st, a);
+          }
+          return hipGetLastError();
+        }
         if (variant == 5) {
           if (a.loss == 0) hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 0, false>), dim3(grid), dim3(1024), 0, st, a);
           else hipLaunchKernelGGL((fused_small_lds_kernel<128, 1024, 1, false>), dim3(grid), dim3(1024), 0, st, a);

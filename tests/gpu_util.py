@@ -206,6 +206,8 @@ def kernel_instance(prob, tune, threads):
     if prob.N >= 256:
         return f"fused_big_kernel<{prob.N},{threads},{loss}>"
     if prob.S > 1:
+        if prob.N == 128 and (tune or {}).get("variant", 0) >= 5:
+            return f"fused_small_lds_ms_kernel<{prob.N},{threads},{loss}>"
         return f"fused_small_ms_kernel<{prob.N},{threads},{loss}>"
     v = (tune or {}).get("variant", 0) if prob.N >= 64 else 0
     if prob.N == 128 and v >= 5:

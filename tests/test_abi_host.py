@@ -74,12 +74,11 @@ def test_status_strings_and_version():
 
 @pytest.mark.parametrize("frame,variant,status,kw", [
     (128, 7, 1, {}), (64, 5, 1, {}), (256, 2, 1, {}), (512, 4, 1, {}), (64, -1, 1, {}),
-    (128, 5, 7, {"n_slices": 2, "lambda_z": 10.0}), (128, 6, 7, {"n_slices": 3, "lambda_z": 10.0}),
     (128, 5, 7, {"det_lambda_z": 100.0}), (128, 6, 7, {"subpixel": "fourier"})])
 def test_plan_rejects_tune_outside_the_layouts(frame, variant, status, kw):
     """Implementation choices outside a frame size's layouts are refused before any
-    device memory is touched (0-4 on chip, 5-6 only at 128^2 with one slice, 0-1 for the
-    four-step frames)."""
+    device memory is touched (0-4 on chip, 5-6 only at 128^2 with the far field and the
+    bilinear patch, 0-1 for the four-step frames)."""
     mod = _lib()
     L = mod.lib()
     d = mod.make_desc(frame=frame, obj_h=3 * frame, obj_w=3 * frame, **kw)

@@ -36,7 +36,8 @@ def test_candidates_four_step_and_multislice(mi355x):
     assert {x["mode_groups"] for x in c if "mode_groups" in x} == {15}
     assert not any("probe_stage" in x for x in c)            # several eigenprobes are staged anyway
     ms = autotune.plan_candidates(128, 2, 8, K=100, split_ok=True, E=1)
-    assert not any("mode_groups" in x or "probe_stage" in x or x["variant"] >= 5 for x in ms)
+    assert not any("mode_groups" in x or "probe_stage" in x for x in ms)
+    assert {(x["variant"], x["recompute"]) for x in ms if x["variant"] >= 5} == {(5, 0), (5, 1)}
 
 
 def test_shape_key_buckets_positions(mi355x):

@@ -96,3 +96,51 @@ def test_lds_layouts_drop_bad_positions(variant):
     assert np.all(got["g_pos"][[7, 21, 30]] == 0)
     got["g_pos"] = got["g_pos"][keep]
     compare(got, ref, grads, tag=f"LDS layout {variant} bad positions")
+
+
+@pytest.mark.parametrize("recompute", [0, 1])
+def test_lds_multislice_config3_structure(recompute):
+    """The LDS-resident multislice kernel (variant 5 with several slices), incident waves
+    stored or recomputed, with the slice-spacing gradient dL/d(lambda z): config 3
+    structure (128^2, 2 modes, weak-phase slices, lambda z = 81.92 px^2) with 3 slices of
+    300^2 and 90 positions on 16 workgroups."""
+    from gpu_util import case
+    start, I = case(3, H=300, K=90, S=3)
+    grads = ("obj", "probe", "pos", "lambda_z")
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": 5, "recompute": recompute, "grid": 16}), start, I, grads)
+    compare(got, ref, grads, tag=f"LDS multislice recompute={recompute}")
+    assert got["flags"] == 0
+    # without the slice-spacing gradient (the other instantiation)
+    grads = ("obj", "probe", "pos")
+    got = run_gpu(_plan(start, tune={"variant": 5, "recompute": recompute, "grid": 16}), start, I, grads)
+    compare(got, {k: v for k, v in ref.items() if k != "g_lambda_z"}, grads, tag=f"LDS multislice no lz")
+
+
+@pytest.mark.parametrize("S,M,E,loss", [(2, 1, 1, "poisson"), (4, 2, 2, "amplitude")])
+def test_lds_multislice_shapes(S, M, E, loss):
+    """Slice counts, modes, OPR eigenprobes with weight gradients and both losses."""
+    start, I = custom_problem(840 + S + M, 128, M, E, S, 360, 48, lz=16.0, loss=loss,
+                              weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos", "lambda_z") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": 6, "recompute": 0, "grid": 16}), start, I, grads)
+    compare(got, ref, grads, tag=f"LDS multislice S={S} M={M} E={E} {loss}")
+    assert got["flags"] == 0
+
+
+def test_lds_multislice_apply_A_AH():
+    """The multislice linear map and its adjoint through the LDS-resident kernel."""
+    torch = torch_cuda()
+    p, _ = custom_problem(860, 128, 2, 1, 3, 384, 30, lz=16.0)
+    plan = _plan(p, tune={"variant": 5, "grid": 16})
+    Psi = plan.apply_A(dev(p.obj), dev(p.probe), dev(p.positions))
+    ref = oracle.apply_A(p.obj, p.probe, p.positions, lambda_z=p.lambda_z)
+    rng = np.random.default_rng(7)
+    Y = (rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)).astype(np.complex64)
+    gO, gU = plan.apply_AH(dev(Y), dev(p.obj), dev(p.probe), dev(p.positions))
+    torch.cuda.synchronize()
+    rO, rU = oracle.apply_AH(Y, p.obj, p.probe, p.positions, lambda_z=p.lambda_z)
+    e = (rel_l2(Psi.cpu().numpy(), ref), rel_l2(gO.cpu().numpy(), rO), rel_l2(gU.cpu().numpy(), rU))
+    print(f"LDS multislice apply_A {e[0]:.2e} apply_AH obj {e[1]:.2e} probe {e[2]:.2e}", flush=True)
+    assert e[0] <= 1e-5 and e[1] <= 1e-4 and e[2] <= 1e-4
