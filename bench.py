@@ -207,7 +207,8 @@ def kernel_name(plan, prob, tune):
         if prob.N >= 256:
             return "split_big_kernel<%d, %d, 1/2> + split_loss_nat_kernel<%d> (mode groups %d)" % (
                 prob.N, info["threads"], loss, groups)
-        return "split_forward/loss/adjoint_kernel<%d, %d> (mode groups %d)" % (prob.N, info["threads"], groups)
+        lds = "_lds" if prob.N == 128 and (tune or {}).get("variant", 0) >= 5 else ""
+        return "split_forward/loss/adjoint%s_kernel<%d, %d> (mode groups %d)" % (lds, prob.N, info["threads"], groups)
     if prob.N >= 256:
         return "fused_big_kernel<%d, %d, %d>" % (prob.N, info["threads"], loss)
     if prob.S > 1:

@@ -115,7 +115,7 @@ def plan_candidates(N: int, M: int, S: int, K: int = 0, split_ok: bool = True, E
         for G in groups:
             if G < 2:
                 continue
-            for v in ([0, 4] if N in (64, 128) else [0]):
+            for v in ([0, 4] if N in (64, 128) else [0]) + ([5] if N == 128 and lds_ok else []):
                 out.append({"variant": v, "recompute": 0, "grid": 0, "mode_groups": G})
     return out
 

@@ -602,10 +602,9 @@ ptyhip_status ptyhip_plan_create_ex(const ptyhip_desc* desc, int32_t max_positio
                tune->plain_chunk < 0 || tune->recompute < 0 || tune->mode_groups < 0 || tune->probe_stage < 0 ||
                tune->probe_stage > 1))
     return PTYHIP_EINVAL;
-  // the LDS-resident 128^2 layouts model the far field and the bilinear patch, with whole
-  // positions per workgroup
+  // the LDS-resident 128^2 layouts model the far field and the bilinear patch
   if (tune && desc->frame == 128 && tune->variant >= 5 &&
-      (desc->propagation != PTYHIP_PROP_FAR || desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR || tune->mode_groups > 1))
+      (desc->propagation != PTYHIP_PROP_FAR || desc->subpixel != PTYHIP_SUBPIXEL_BILINEAR))
     return PTYHIP_EUNSUPPORTED;
   if (tune && tune->mode_groups > 1 &&
       (desc->n_slices != 1 || desc->propagation != PTYHIP_PROP_FAR ||

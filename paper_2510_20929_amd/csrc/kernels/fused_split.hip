@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "launch.hpp"
+#include "lds_body.hpp"
 #include "small_body.hpp"
 #include "split_loss.hpp"
 
@@ -80,7 +81,9 @@ __global__ __launch_bounds__(T) void split_forward_kernel(CallArgs a) {
 // measurement at the element's centred pixel, I_pred there, cfr = 2 dl/dI / (K_norm N^2)
 // in the frame layout; the chunk's loss sum goes to lpart[k][c]. Chunks keep many
 // workgroups busy when a call has few positions.
-template <int N, int T, int LOSS>
+// LDSL: the frames come from the LDS-resident layout (element e of thread t is frequency
+// (FrameLds::row(t, e), FrameLds::col(t))) instead of Frame2D's layout D.
+template <int N, int T, int LOSS, bool LDSL = false>
 __global__ __launch_bounds__(256) void split_loss_chunk_kernel(CallArgs a, double* __restrict__ lpart) {
   using C = SmallCtx<N, T>;
   __shared__ double red[2 * (256 / WAVE)];
@@ -99,7 +102,10 @@ __global__ __launch_bounds__(256) void split_loss_chunk_kernel(CallArgs a, doubl
     for (int j = 0; j < PP; ++j) {
       fj[j] = f0 + int(threadIdx.x) + 256 * j;
       on[j] = fj[j] < f1;
-      cj[j] = on[j] ? C::d_centred(fj[j] % T, fj[j] / T) : 0;
+      if constexpr (LDSL)
+        cj[j] = on[j] ? centred_index(FrameLds<N, T>::row(fj[j] % T, fj[j] / T), FrameLds<N, T>::col(fj[j] % T), N) : 0;
+      else
+        cj[j] = on[j] ? C::d_centred(fj[j] % T, fj[j] / T) : 0;
     }
     if (!p.ok) {
       if (a.ipred)
@@ -236,6 +242,216 @@ __global__ __launch_bounds__(T) void split_adjoint_kernel(CallArgs a) {
   }
 }
 
+// ----------------------------------------------------------------------------- LDS-resident
+// The forward and adjoint passes with the working frame resident in LDS (128^2, tune
+// variants 5 and 6; the element ownership of lds_body.hpp): the item's patch and its
+// group's running patch gradient stay in registers, the exit wave feeds the row pass and
+// the scaled far field the inverse column pass in registers. Partial intensities and cfr
+// are stored in the column layout (element e of thread t at e T + t).
+template <int N, int T>
+__global__ __launch_bounds__(T) void split_forward_lds_kernel(CallArgs a) {
+  using F = FrameLds<N, T>;
+  constexpr int EL = F::EL, NN = N * N, N1 = F::N1;
+  __shared__ LdsShared<N, T> sh;
+  for (int i = threadIdx.x; i < N; i += T) sh.tws[i] = a.tw[i];
+  const float inv_n = 1.f / float(N);
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const BufFrame pb(a.probe, uint32_t(size_t(a.E) * a.M * NN * sizeof(float2)));
+  const int items = a.K * a.groups;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int k = it / a.groups, g = it - k * a.groups;
+    const int m0 = g * a.group_modes, m1 = min(a.M, m0 + a.group_modes);
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    if (!p.ok) continue;  // the loss launch drops the position
+    __syncthreads();      // the previous item is done with the weights and the LDS
+    if (a.weights && int(threadIdx.x) < a.E) sh.wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
+    __syncthreads();
+    const float* wk = a.weights ? sh.wsh : nullptr;
+    const int t = opaque_tid();
+    const int vp = ((t / N1) * N + t % N1) * 8;
+    float2 o[EL];
+#pragma unroll
+    for (int i = 0; i < EL; ++i) o[i] = bilinear(a.obj, a.W, p, t / N1, t % N1 + N1 * i);
+    float cf[EL];
+#pragma unroll
+    for (int e = 0; e < EL; ++e) cf[e] = 0.f;
+    for (int m = m0; m < m1; ++m) {
+      float2 u[EL];
+#pragma unroll
+      for (int i = 0; i < EL; ++i) {
+        float2 P;
+        if (wk == nullptr) {
+          P = pb.ld(vp, (m * NN + N1 * i) * 8);
+        } else {
+          P = make_float2(0.f, 0.f);
+          for (int e = 0; e < a.E; ++e) {
+            const float2 q = pb.ld(vp, ((e * a.M + m) * NN + N1 * i) * 8);
+            P.x = fmaf(wk[e], q.x, P.x);
+            P.y = fmaf(wk[e], q.y, P.y);
+          }
+        }
+        u[i] = cmul(P, o[i]);
+      }
+      F::template rows_from<false>(sh.lds, sh.tws, 1.f, u);
+      __syncthreads();
+      float2 v[EL];
+      F::cols_to_regs(sh.lds, sh.tws, inv_n, v);
+#pragma unroll
+      for (int e = 0; e < EL; ++e) cf[e] += cabs2(v[e]);
+      __syncthreads();  // column phase done before the next exit wave
+    }
+    float* dst = a.ipart + size_t(it) * NN;
+#pragma unroll
+    for (int e = 0; e < EL; ++e) dst[size_t(e) * T + t] = cf[e];
+  }
+}
+
+template <int N, int T>
+__global__ __launch_bounds__(T) void split_adjoint_lds_kernel(CallArgs a) {
+  using F = FrameLds<N, T>;
+  constexpr int EL = F::EL, NN = N * N, N1 = F::N1, P = F::P;
+  __shared__ LdsShared<N, T> sh;
+  float2* lds = sh.lds;
+  for (int i = threadIdx.x; i < N; i += T) sh.tws[i] = a.tw[i];
+  const float inv_n = 1.f / float(N);
+  const bool want_pos = (a.want & WANT_POS) && a.mode == MODE_FWD_ADJ;
+  const bool want_probe = (a.want & WANT_PROBE) != 0;
+  const BufFrame pb(a.probe, uint32_t(size_t(a.E) * a.M * NN * sizeof(float2)));
+  const int items = a.K * a.groups;
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    const int k = it / a.groups, g = it - k * a.groups;
+    const int m0 = g * a.group_modes, m1 = min(a.M, m0 + a.group_modes);
+    if (!a.kvalid[k]) {
+      const int tid = threadIdx.x;
+      if (tid == 0) {
+        a.wvalid[it] = 0;
+        if (a.pos_part) {
+          a.pos_part[2 * size_t(it)] = 0.0;
+          a.pos_part[2 * size_t(it) + 1] = 0.0;
+        }
+      }
+      if (a.w_part && tid < a.E) a.w_part[size_t(it) * a.E + tid] = 0.0;
+      continue;
+    }
+    const PosInfo p = parse_position(a.pos, k, N, a.H, a.W, want_pos);
+    __syncthreads();  // the previous item is done with LDS, weights and sums
+    if (a.weights && int(threadIdx.x) < a.E) sh.wsh[threadIdx.x] = a.weights[size_t(k) * a.E + threadIdx.x];
+    for (int i = threadIdx.x; i < MAX_EIG * (T / WAVE); i += T) sh.wacc[i] = 0.0;
+    __syncthreads();
+    // the item's modes, with the weighted (OPR) and unweighted probe loops as separate
+    // instantiations
+    auto item = [&](auto wc) {
+      constexpr bool WT = decltype(wc)::value;
+      const float* wk = WT ? sh.wsh : nullptr;
+      const int t = opaque_tid();
+      const int vp = ((t / N1) * N + t % N1) * 8;
+      auto probe_r = [&](int m, int i) -> float2 {
+        if constexpr (!WT) return pb.ld(vp, (m * NN + N1 * i) * 8);
+        float2 P = make_float2(0.f, 0.f);
+        for (int e = 0; e < a.E; ++e) {
+          const float2 q = pb.ld(vp, ((e * a.M + m) * NN + N1 * i) * 8);
+          P.x = fmaf(wk[e], q.x, P.x);
+          P.y = fmaf(wk[e], q.y, P.y);
+        }
+        return P;
+      };
+      float2 o[EL];
+#pragma unroll
+      for (int i = 0; i < EL; ++i) o[i] = bilinear(a.obj, a.W, p, t / N1, t % N1 + N1 * i);
+      const BufFrame cb(a.cfr + size_t(k) * NN, uint32_t(NN * sizeof(float)));  // cfr of position k
+      float2 go[EL];
+      for (int m = m0; m < m1; ++m) {
+        {
+          float2 u[EL];
+#pragma unroll
+          for (int i = 0; i < EL; ++i) {
+            u[i] = cmul(probe_r(m, i), o[i]);
+            if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+          F::template rows_from<false>(lds, sh.tws, 1.f, u);
+        }
+        __syncthreads();
+        {
+          float2 v[EL], u[EL];
+          F::cols_to_regs(lds, sh.tws, inv_n, v);
+#pragma unroll
+          for (int n2 = 0; n2 < EL; ++n2) {
+            const int e = F::reg_of(n2);
+            u[n2] = cscale(v[e], cb.ldf(t * 4, e * T * 4));
+          }
+          F::template cols_from<true>(lds, sh.tws, 1.f, u);
+        }
+        __syncthreads();
+        F::template rows<true>(lds, sh.tws, inv_n);
+        // probe side: the staged probe-wave gradient conj(o) g_m (natural pixel order) and
+        // the OPR weight terms
+        if (want_probe && a.gpstage) {
+          float2* st = a.gpstage + (size_t(k) * a.M + m) * NN;
+#pragma unroll
+          for (int i = 0; i < EL; ++i) {
+            st[(t / N1) * N + t % N1 + N1 * i] = cmulc(o[i], lds[(t / N1) * P + t % N1 + N1 * i]);
+            if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        if (WT && (a.want & WANT_WEIGHTS)) {
+          for (int e = 0; e < a.E; ++e) {
+            float sf = 0.f;
+#pragma unroll
+            for (int i = 0; i < EL; ++i) {
+              sf += cdotre(cmulc(o[i], lds[(t / N1) * P + t % N1 + N1 * i]), pb.ld(vp, ((e * a.M + m) * NN + N1 * i) * 8));
+              if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            const double sw = wave_sum(double(sf));
+            if ((threadIdx.x & (WAVE - 1)) == 0) sh.wacc[e * (T / WAVE) + threadIdx.x / WAVE] += sw;
+          }
+        }
+        // object side: the group's running patch gradient; the last mode's lands in the frame
+        auto pass = [&](auto first_c, auto last_c) {
+          constexpr bool FIRST = decltype(first_c)::value, LAST = decltype(last_c)::value;
+#pragma unroll
+          for (int i = 0; i < EL; ++i) {
+            const int c = (t / N1) * P + t % N1 + N1 * i;
+            float2 gg = cmulc(probe_r(m, i), lds[c]);
+            if constexpr (!FIRST) gg = cadd(gg, go[i]);
+            if constexpr (LAST) lds[c] = gg;
+            else go[i] = gg;
+            if (i % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+        };
+        using T0 = std::false_type;
+        using T1 = std::true_type;
+        const bool first = m == m0, last = m == m1 - 1;
+        if (first) {
+          if (last) pass(T1{}, T1{});
+          else pass(T1{}, T0{});
+        } else {
+          if (last) pass(T0{}, T1{});
+          else pass(T0{}, T0{});
+        }
+      }
+    };
+    if (a.weights) item(std::true_type{});
+    else item(std::false_type{});
+    __syncthreads();
+    double gy = 0.0, gx = 0.0;
+    window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(it) * (N + 1) * (N + 1) : nullptr, gy, gx);
+    finish_position<N, T>(a, it, gy, gx, sh.red, sh.wacc);
+  }
+}
+
+static hipError_t launch_split_lds(const CallArgs& a, int items_grid, double* lpart, hipStream_t st) {
+  constexpr int N = 128, T = 1024;
+  hipLaunchKernelGGL((split_forward_lds_kernel<N, T>), dim3(items_grid), dim3(T), 0, st, a);
+  const int nch = split_loss_chunks(N);
+  const dim3 lg(unsigned(nch), unsigned(a.K < 65535 ? a.K : 65535));
+  if (a.loss == 0) hipLaunchKernelGGL((split_loss_chunk_kernel<N, T, 0, true>), lg, dim3(256), 0, st, a, lpart);
+  else hipLaunchKernelGGL((split_loss_chunk_kernel<N, T, 1, true>), lg, dim3(256), 0, st, a, lpart);
+  hipLaunchKernelGGL(split_loss_total_small_kernel, dim3(unsigned((a.K + 255) / 256)), dim3(256), 0, st, a, N, nch,
+                     (const double*)lpart);
+  if (a.mode == MODE_FWD_ADJ) hipLaunchKernelGGL((split_adjoint_lds_kernel<N, T>), dim3(items_grid), dim3(T), 0, st, a);
+  return hipGetLastError();
+}
+
 template <int N, int T>
 static hipError_t launch_split_t(const CallArgs& a, int items_grid, double* lpart, hipStream_t st) {
   hipLaunchKernelGGL((split_forward_kernel<N, T>), dim3(items_grid), dim3(T), 0, st, a);
@@ -261,7 +477,9 @@ hipError_t launch_fused_split(const CallArgs& a, int N, int variant, int grid, d
     case 32: return launch_split_t<32, 128>(a, g_items, lpart, st);
     case 64: return T == 256 ? launch_split_t<64, 256>(a, g_items, lpart, st)
                              : launch_split_t<64, 512>(a, g_items, lpart, st);
-    case 128: return T == 1024 ? launch_split_t<128, 1024>(a, g_items, lpart, st)
+    case 128:
+      if (variant >= 5) return launch_split_lds(a, g_items, lpart, st);
+      return T == 1024 ? launch_split_t<128, 1024>(a, g_items, lpart, st)
                                : launch_split_t<128, 512>(a, g_items, lpart, st);
     default: return hipErrorInvalidValue;
   }

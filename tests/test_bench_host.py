@@ -50,3 +50,10 @@ def test_kernel_names_of_the_mode_split_form():
     assert bench.kernel_name(plan, p512, {"variant": 0}) == "fused_big_kernel<512, 1024, 0>"
     p1 = types.SimpleNamespace(N=128, M=4, S=1, loss="poisson")
     assert bench.kernel_name(plan, p1, {"variant": 4}) == "fused_small_kernel<128, 1024, 1, true, false>"
+    # the LDS-resident layouts
+    assert bench.kernel_name(plan, p1, {"variant": 5}) == "fused_small_lds_kernel<128, 1024, 1, false>"
+    assert bench.kernel_name(plan, p1, {"variant": 6}) == "fused_small_lds_kernel<128, 1024, 1, true>"
+    assert bench.kernel_name(plan, p128, {"variant": 5, "mode_groups": 15}).startswith(
+        "split_forward/loss/adjoint_lds_kernel<128, 1024>")
+    p3 = types.SimpleNamespace(N=128, M=2, S=8, loss="amplitude")
+    assert bench.kernel_name(plan, p3, {"variant": 5}) == "fused_small_lds_ms_kernel<128, 1024, 0>"

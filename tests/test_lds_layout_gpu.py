@@ -144,3 +144,44 @@ def test_lds_multislice_apply_A_AH():
     e = (rel_l2(Psi.cpu().numpy(), ref), rel_l2(gO.cpu().numpy(), rO), rel_l2(gU.cpu().numpy(), rU))
     print(f"LDS multislice apply_A {e[0]:.2e} apply_AH obj {e[1]:.2e} probe {e[2]:.2e}", flush=True)
     assert e[0] <= 1e-5 and e[1] <= 1e-4 and e[2] <= 1e-4
+
+
+@pytest.mark.parametrize("M,E,G,loss", [(4, 1, 2, "poisson"), (4, 1, 4, "amplitude"), (15, 3, 4, "amplitude"),
+                                        (5, 2, 2, "poisson")])
+def test_lds_mode_split_form(M, E, G, loss):
+    """The mode-split form (each position's modes in G groups: forward, loss and adjoint
+    launches) with the LDS-resident layout, against the oracle: eigenprobe weights or
+    none, groups of unequal size, every gradient, on 8 workgroups (several items each)."""
+    start, I = custom_problem(880 + M + E + G, 128, M, E, 1, 384, 20, loss=loss, weights="opr" if E > 1 else None)
+    grads = ("obj", "probe", "pos") + (("weights",) if E > 1 else ())
+    ref = run_oracle(start, I, grads)
+    got = run_gpu(_plan(start, tune={"variant": 5, "mode_groups": G, "grid": 8}), start, I, grads)
+    compare(got, ref, grads, tag=f"LDS split M={M} E={E} G={G}")
+    assert got["flags"] == 0
+
+
+def test_lds_mode_split_forward_and_bad_position():
+    """Mode-split LDS form: the forward call alone (loss and predicted intensities in the
+    column layout's detector mapping), and a position whose window leaves the object
+    (latched and dropped, the rest exact)."""
+    from dataclasses import replace
+    from paper_2510_20929_amd import FLAG_BOUNDS
+    torch = torch_cuda()
+    start, I = custom_problem(890, 128, 6, 1, 1, 360, 24, loss="poisson")
+    plan = _plan(start, tune={"variant": 5, "mode_groups": 3, "grid": 8})
+    ipred = torch.zeros((start.K, 128, 128), dtype=torch.float32, device="cuda")
+    loss = plan.forward(dev(start.obj), dev(start.probe), dev(start.positions), dev(I), I_pred=ipred)
+    torch.cuda.synchronize()
+    ref_l, ref_I = oracle.forward(start.obj, start.probe, start.positions, I, loss=start.loss, eps=start.eps)
+    compare({"loss": float(loss.cpu()[0]), "I_pred": ipred.cpu().numpy()}, {"loss": ref_l, "I_pred": ref_I}, (),
+            tag="LDS split forward")
+    pos = start.positions.copy()
+    pos[5] = (360.0 - 10.0, 3.0)
+    q = replace(start, positions=pos)
+    keep = np.array([k for k in range(start.K) if k != 5])
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(q.subset(keep), I[keep], grads, norm_count=start.K)
+    got = run_gpu(_plan(q, tune={"variant": 5, "mode_groups": 3, "grid": 8}), q, I, grads, want_ipred=False)
+    assert got["flags"] & FLAG_BOUNDS
+    got["g_pos"] = got["g_pos"][keep]
+    compare(got, ref, grads, tag="LDS split bad position")
