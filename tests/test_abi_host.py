@@ -86,3 +86,18 @@ def test_plan_rejects_tune_outside_the_layouts(frame, variant, status, kw):
     h = ctypes.c_void_p(1)
     assert L.ptyhip_plan_create_ex(ctypes.byref(d), 10, ctypes.byref(t), ctypes.byref(h)) == status
     assert h.value is None
+
+
+@pytest.mark.parametrize("variant,status", [(5, 1), (6, 1), (-1, 1)])
+def test_static_entry_point_refuses_layouts_it_does_not_run(variant, status):
+    """The allocation-free entry point runs the register-resident on-chip layouts 0-4 only;
+    other tune variants are refused before any device call (non-null dummy pointers: the
+    call returns before it would read them)."""
+    mod = _lib()
+    L = mod.lib()
+    d = mod.make_desc(frame=128, n_modes=2, obj_h=400, obj_w=400)
+    t = mod.Tune(variant=variant)
+    dummy = ctypes.c_void_p(16)
+    st = L.ptyhip_forward_adjoint_static(ctypes.byref(d), ctypes.byref(t), None, 4, 3, dummy, dummy, None, dummy,
+                                         dummy, dummy, None, None, None, None, None, None)
+    assert st == status
