@@ -58,7 +58,13 @@ __device__ __forceinline__ void lds_body(const CallArgs& a, LdsShared<N, T>& sh,
   float2* scr = a.scratch + size_t(wg) * a.scratch_stride;
   const BufFrame sb(scr, uint32_t(a.scratch_stride * sizeof(float2)));
   const int pacc_b = int(a.pacc_off * sizeof(float2));
-  if (adj && a.zero_acc && want_probe && !a.gpstage) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  // A call that starts the accumulator from zero does not clear it first: the workgroup's
+  // first position with a finished adjoint writes every accumulator frame without reading
+  // it (acc_fresh), and a workgroup that finishes none clears it at the end. That needs
+  // every frame written per position, i.e. one eigenprobe or per-position weights.
+  const bool acc_lazy = adj && a.zero_acc && want_probe && !a.gpstage && (a.weights || a.E == 1);
+  if (adj && a.zero_acc && want_probe && !a.gpstage && !acc_lazy) zero_probe_acc<N, T>(a, scr + a.pacc_off);
+  bool acc_fresh = acc_lazy;
   // pixel (y, x) = (t / N1, t mod N1 + N1 i) of element i of thread t: its index, its
   // LDS cell, and the thread part of its byte offset; element loops issue four
   // elements' loads at a time (a scheduling barrier after every fourth)
@@ -247,8 +253,13 @@ __device__ __forceinline__ void lds_body(const CallArgs& a, LdsShared<N, T>& sh,
 #pragma unroll
             for (int i0 = 0; i0 < EL; i0 += 4) {
               float2 g[4];
+              if (acc_fresh) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u) g[u] = sb.ld(vpix(t), fb + N1 * (i0 + u) * 8);
+                for (int u = 0; u < 4; ++u) g[u] = make_float2(0.f, 0.f);
+              } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) g[u] = sb.ld(vpix(t), fb + N1 * (i0 + u) * 8);
+              }
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
                 const float2 gp = cmulc(o[i0 + u], lds[cell(t, i0 + u)]);
@@ -295,6 +306,7 @@ __device__ __forceinline__ void lds_body(const CallArgs& a, LdsShared<N, T>& sh,
       }
     }
 
+    acc_fresh = false;  // every accumulator frame holds this position's terms now
     __syncthreads();
     double gy = 0.0, gx = 0.0;
     window_pass<N, T>(a, p, lds, a.obj, a.gwin ? a.gwin + size_t(k) * (N + 1) * (N + 1) : nullptr, gy, gx);
@@ -303,6 +315,7 @@ __device__ __forceinline__ void lds_body(const CallArgs& a, LdsShared<N, T>& sh,
     if (a.weights) position(std::true_type{});
     else position(std::false_type{});
   }
+  if (acc_fresh) zero_probe_acc<N, T>(a, scr + a.pacc_off);
 }
 
 }  // namespace ptyhip
