@@ -185,3 +185,35 @@ def test_lds_mode_split_forward_and_bad_position():
     assert got["flags"] & FLAG_BOUNDS
     got["g_pos"] = got["g_pos"][keep]
     compare(got, ref, grads, tag="LDS split bad position")
+
+
+@pytest.mark.parametrize("variant", [5, 6])
+def test_lds_layouts_workgroup_without_finished_position(variant):
+    """A workgroup starts its probe-gradient accumulator at its first position whose
+    adjoint finishes (written, not added), and one whose positions all drop clears it after
+    its last position. 40 positions on 16 workgroups: workgroup 3 (positions 3, 19, 35)
+    drops every position (two windows leaving the object, a non-finite pattern), workgroup
+    9 drops its first (a non-finite pattern). Two calls in a row on one plan, the second
+    finding the first call's accumulators in the scratch, both match the oracle on the
+    kept positions."""
+    from dataclasses import replace
+    from paper_2510_20929_amd import FLAG_BOUNDS, FLAG_NONFINITE
+    start, I = custom_problem(795 + variant, 128, 2, 1, 1, 330, 40, loss="amplitude")
+    pos = start.positions.copy()
+    I = I.copy()
+    pos[3] = (330.0 - 1.5, 5.0)
+    pos[19] = (5.0, 330.0 - 1.5)
+    I[35, 0, 0] = np.nan
+    I[9, 2, 2] = np.nan
+    q = replace(start, positions=pos)
+    drop = [3, 9, 19, 35]
+    keep = np.array([k for k in range(start.K) if k not in drop])
+    grads = ("obj", "probe", "pos")
+    ref = run_oracle(q.subset(keep), I[keep], grads, norm_count=start.K)
+    plan = _plan(q, tune={"variant": variant, "recompute": 1, "grid": 16})
+    for call in range(2):
+        got = run_gpu(plan, q, I, grads, want_ipred=False)
+        assert got["flags"] & FLAG_BOUNDS and got["flags"] & FLAG_NONFINITE
+        assert np.all(got["g_pos"][drop] == 0)
+        got["g_pos"] = got["g_pos"][keep]
+        compare(got, ref, grads, tag=f"LDS layout {variant} workgroup without a finished position, call {call}")
